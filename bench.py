@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the full-state simulation hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = plan the circuit on the host (booster, diagonal detector, stages,
+fusion) and execute it on the GPU from |0...0> to the final state, for the
+30-qubit random layered circuit (40 layers, 2,680 gates, complex128).  The
+state (16 GiB) stays resident in HBM.  Prints one JSON line:
+
+* value: input gates applied per second over the timed steps (gate-apps/s);
+* roofline: the dominant kernel's achieved rate against the MI355X peak that
+  bounds it, from HIP events around its launches inside the timed steps;
+* cpu_baseline: the CPU oracle (one gate per full pass, complex128) timed on a
+  bounded prefix of the same circuit at the same size on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_workload(name, dtype, opt, steps, warmup, profile=True):
+    import torch
+    from paper_2604_12256_amd import qsim
+    from paper_2604_12256_amd import workloads as W
+    n, gates = W.config_circuit(name)
+    sim = qsim.Simulator(n, dtype=dtype, opt=opt)
+    sim.set_profiling(profile)
+    for i in range(warmup):
+        sim.load(gates)
+        sim.run()
+        log(f"[bench] {name} warmup {i + 1}/{warmup}: {sim.stats()['run_ms']:.1f} ms")
+    per_kind = {}
+    plan_ms = run_ms = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        sim.load(gates)
+        sim.run()
+        st = sim.stats()
+        plan_ms += st["plan_ms"]
+        run_ms += st["run_ms"]
+        if profile:
+            for t in sim.op_timings():
+                if t["buffer"] != 0:
+                    continue
+                d = per_kind.setdefault(t["kind"], {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+                d["ms"] += t["ms"]
+                d["launches"] += 1
+                d["flops"] += t["flops"]
+                d["bytes"] += t["bytes"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.stats()
+    norm = sim.norm()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"n": n, "gates": len(gates), "wall_s": t1 - t0, "plan_ms": plan_ms / steps, "run_ms": run_ms / steps,
+            "per_kind": per_kind, "stats": st, "norm": norm}
+
+
+def roofline(per_kind, dtype):
+    kind = max(per_kind, key=lambda k: per_kind[k]["ms"])
+    d = per_kind[kind]
+    avg_s = d["ms"] / d["launches"] / 1e3
+    flops = d["flops"] / d["launches"]
+    byts = d["bytes"] / d["launches"]
+    peak_fl = FP64_PEAK_TFLOPS if dtype == "c128" else FP32_PEAK_TFLOPS
+    intensity = flops / byts if byts else float("inf")
+    ridge = peak_fl * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity > ridge:
+        ach = flops / avg_s / 1e12
+        r = {"bound": "alu", "achieved": round(ach, 3), "peak": peak_fl, "unit": "TFLOP/s",
+             "frac": round(ach / peak_fl, 4)}
+    else:
+        ach = byts / avg_s / 1e9
+        r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(ach / HBM_PEAK_GBS, 4)}
+    r.update({"kernel": {"STAGE": "k_stage", "DENSE": "k_dense", "DIAG": "k_diag", "KRON": "k_kron",
+                         "INIT": "k_init"}.get(kind, kind),
+              "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": d["launches"] // max(1, 1),
+              "flops_per_launch": flops, "bytes_per_launch": byts,
+              "hbm_GBps_of_kernel": round(byts / avg_s / 1e9, 1), "traffic": None})
+    return r
+
+
+def cpu_baseline(name, n_prefix):
+    """Oracle on the first n_prefix gates of the same circuit at full size."""
+    import numpy as np
+    from oracle import oracle
+    from paper_2604_12256_amd import workloads as W
+    oracle.build(force=False)
+    n, gates = W.config_circuit(name)
+    sample = gates[:n_prefix]
+    t0 = time.perf_counter()
+    state = oracle.run(n, sample)
+    dt = time.perf_counter() - t0
+    del state
+    return {"value": round(len(sample) / dt, 4), "unit": "gate-apps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {len(sample)} gates of {name} ({n} qubits, full 2^{n} complex128 state, "
+                      f"incl. |0> init), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="layered30")
+    ap.add_argument("--dtype", default="c128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-prefix", type=int, default=12)
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the state vector is not sharded across "
+              "GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    from paper_2604_12256_amd import qsim
+    log(f"[bench] workload {args.workload} {args.dtype} steps={args.steps} warmup={args.warmup}")
+    r = run_workload(args.workload, args.dtype, qsim.OPT_ALL, args.steps, args.warmup)
+    ms_per_step = r["wall_s"] / args.steps * 1e3
+    value = r["gates"] / (ms_per_step / 1e3)
+    st = r["stats"]
+    hbm = st["algorithmic_bytes"] / (r["run_ms"] / 1e3) / 1e9
+    out = {
+        "metric": "gate-apps/s + HBM GB/s (% peak) at 30q; served p50/p99 latency vs plain",
+        "value": round(value, 2),
+        "unit": "gate-apps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.dtype == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {r['n']}-qubit random layered circuit, 40 layers "
+                               f"(Haar U(2) on every qubit, CZ on floor(n/4) random disjoint pairs, RZ on every "
+                               f"qubit), {r['gates']} gates, seed 1, {args.dtype}, |0...0> init, all optimiser "
+                               f"passes (booster, diagonal detector, cache-blocked stages, fusion)",
+                   "qubits": r["n"], "gates": r["gates"], "state_GiB": (16 if args.dtype == 'c128' else 8) *
+                   2 ** r["n"] / 2 ** 30},
+        "plan_ms": round(r["plan_ms"], 3),
+        "run_ms": round(r["run_ms"], 3),
+        "hbm_GBps": round(hbm, 1),
+        "hbm_frac": round(hbm / HBM_PEAK_GBS, 4),
+        "full_passes": st["full_passes"],
+        "stages": st["n_stages"],
+        "plan_flops": st["flops"],
+        "norm_error": abs(r["norm"] - 1.0),
+        "roofline": roofline(r["per_kind"], args.dtype),
+        "per_kind_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in r["per_kind"].items()},
+    }
+    if not args.no_secondary:
+        d = run_workload("diag30", "c128", qsim.OPT_ALL, 3, 1)
+        ms = d["wall_s"] / 3 * 1e3
+        dh = d["stats"]["algorithmic_bytes"] / (d["run_ms"] / 1e3) / 1e9
+        out["secondary"] = {"workload": "diag30: 30-qubit diagonal-heavy circuit, 200 gates (160 diagonal), "
+                                        "complex128, all passes",
+                            "gate_apps_per_s": round(d["gates"] / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+                            "hbm_GBps": round(dh, 1), "hbm_frac": round(dh / HBM_PEAK_GBS, 4),
+                            "full_passes": d["stats"]["full_passes"],
+                            "roofline": roofline(d["per_kind"], "c128")}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_prefix)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

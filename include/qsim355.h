@@ -1,0 +1,247 @@
+/*
+ * qsim355 -- full-state quantum circuit simulation on one AMD Instinct MI355X.
+ *
+ * C ABI.  Every function returns a sim_status (SIM_OK == 0) unless stated;
+ * no C++ exception crosses this boundary.  A context is not thread-safe;
+ * distinct contexts may be used from distinct threads.
+ *
+ * Semantics (paper Sec. 2.1-2.2, Eq. (1)): an N-qubit state holds 2^N complex
+ * amplitudes a_i, i in [0, 2^N); qubit j is bit j of i.  A k-qubit gate on
+ * the ordered qubit list q[0..k-1] multiplies, for every assignment of the
+ * other bits, the 2^k amplitudes it touches by its 2^k x 2^k matrix, where
+ * bit t of the matrix row/column index is bit q[t] of i (an ascending list
+ * reproduces the two-qubit layout of Sec. 2.2).  sim_run starts from
+ * |0...0> and applies the circuit in input order (gate-by-gate definition,
+ * Alg. 1); every optimisation the library applies (merge booster Sec. 4.4,
+ * diagonal detector Sec. 4.5, cache-blocked stages Alg. 2, gate fusion,
+ * qubit reordering Sec. 2.3) yields that same state up to rounding.
+ *
+ * All indices, amplitudes and probabilities at this boundary are in logical
+ * qubit order; internal qubit remapping is undone by the library.
+ *
+ * Memory: the state vector lives in a caller-owned device buffer (e.g. a
+ * torch tensor) passed in sim_options and must outlive the context.  The
+ * context owns its plan and the small device tables it uploads.  Host output
+ * buffers are caller-owned.
+ */
+#ifndef QSIM355_H
+#define QSIM355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_ctx sim_ctx;
+typedef struct sim_plan sim_plan;
+
+typedef enum {
+    SIM_OK = 0,
+    SIM_E_INVAL = 1,       /* bad argument: qubit >= N, duplicate qubits, k > 6,
+                              NULL data for MATRIX/DIAG, non-unitary MATRIX
+                              (error > 1e-10), non-unit DIAG entry, NULL pointer */
+    SIM_E_NOMEM = 2,       /* a device or host buffer is too small / allocation failed */
+    SIM_E_DEVICE = 3,      /* a HIP runtime error; text from sim_last_error */
+    SIM_E_STATE = 4,       /* call out of order (e.g. outputs before sim_run) */
+    SIM_E_UNSUPPORTED = 5  /* valid request outside what this build implements */
+} sim_status;
+
+typedef enum { SIM_C128 = 0, SIM_C64 = 1 } sim_dtype;
+
+/* Gate kinds.  Matrices of the named gates are the textbook ones:
+ *   H, X, Y, Z, S = diag(1, i), T = diag(1, e^{i pi/4}),
+ *   SX = (1/2)[[1+i, 1-i], [1-i, 1+i]],
+ *   RX/RY/RZ(theta) = exp(-i theta P / 2) for P = X, Y, Z,
+ *   CZ = diag(1, 1, 1, -1), CPHASE(theta) = diag(1, 1, 1, e^{i theta}),
+ *   RZZ(theta) = exp(-i theta Z(x)Z / 2),
+ *   CNOT: q[0] control, q[1] target; SWAP exchanges q[0] and q[1]. */
+typedef enum {
+    SIM_G_MATRIX = 0,  /* data: 2^k x 2^k complex, row-major, interleaved (re, im) FP64 */
+    SIM_G_DIAG = 1,    /* data: 2^k complex diagonal, interleaved (re, im) FP64 */
+    SIM_G_H, SIM_G_X, SIM_G_Y, SIM_G_Z, SIM_G_S, SIM_G_T, SIM_G_SX,
+    SIM_G_RX, SIM_G_RY, SIM_G_RZ,
+    SIM_G_CZ, SIM_G_CNOT, SIM_G_CPHASE, SIM_G_RZZ, SIM_G_SWAP,
+    SIM_G_NKINDS
+} sim_gate_kind;
+
+typedef struct {
+    uint32_t kind;      /* sim_gate_kind */
+    uint32_t nq;        /* number of qubits k (1..6); must equal the kind's arity */
+    uint32_t q[6];      /* ordered qubit list; bit t of the matrix index <-> q[t] */
+    double theta;       /* angle of RX/RY/RZ/CPHASE/RZZ, ignored otherwise */
+    const double *data; /* MATRIX/DIAG payload (host memory, read during the call) */
+} sim_gate;
+
+/* Optimisation passes (bit flags for sim_options.opt). */
+enum {
+    SIM_OPT_DIAG = 1u << 0,    /* diagonal detector (Sec. 4.5, Alg. 8) */
+    SIM_OPT_FUSE = 1u << 1,    /* cost-based gate fusion up to F qubits */
+    SIM_OPT_STAGES = 1u << 2,  /* cache blocking: chunk-resident stages (Alg. 2, Alg. 5) */
+    SIM_OPT_BOOST = 1u << 3,   /* merge booster (Sec. 4.4, Alg. 6-7) */
+    SIM_OPT_ALL = 0xFu
+};
+
+typedef struct {
+    uint32_t opt;          /* SIM_OPT_* flags; 0 = gate by gate (Alg. 1) */
+    uint32_t C;            /* chunk qubits of a stage (0 = default for the dtype) */
+    uint32_t F;            /* max qubits of a fused dense gate (0 = default 5) */
+    uint32_t D;            /* max qubits of a fused diagonal (0 = default 10) */
+    uint32_t B;            /* booster division parameter (0 = default 4) */
+    uint32_t force_fuse_k; /* >0: fusion-only plans fuse greedily to this many qubits
+                              regardless of cost (exercises the MFMA path) */
+    void *dev_state;           /* device buffer, >= 2^N * 16 B (C128) or 8 B (C64) */
+    uint64_t dev_state_bytes;
+    void *stream;              /* hipStream_t the context launches on (NULL = default) */
+} sim_options;
+
+typedef struct {
+    uint64_t n_gates;          /* gates of the loaded circuit */
+    uint64_t n_ops;            /* ops of the executed plan */
+    uint64_t full_passes;      /* read+write passes over the full state */
+    uint64_t write_passes;     /* write-only passes (init, tensor product) */
+    uint64_t read_passes;      /* read-only passes (reductions) of the last output call */
+    uint64_t n_stages;         /* cache-blocked stage ops */
+    uint64_t n_dense;          /* full-pass dense ops */
+    uint64_t n_diag;           /* full-pass diagonal ops */
+    uint64_t n_kron;           /* tensor products */
+    uint64_t n_perm;           /* qubit permutations */
+    uint64_t n_subruns;        /* ops run on booster sub-states */
+    double plan_ms;            /* host optimiser time of the last sim_load_circuit */
+    double run_ms;             /* device time of the last sim_run (HIP events) */
+    double algorithmic_bytes;  /* bytes the plan moves over the full state */
+    double flops;              /* floating-point operations of the plan (estimate) */
+} sim_run_stats;
+
+/* Create a context for an n_qubits state of the given dtype.
+ * opts->dev_state must hold 2^n amplitudes (SIM_E_NOMEM otherwise).
+ * n_qubits: 1..34.  *out receives the context (caller frees with sim_destroy). */
+sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts, sim_ctx **out);
+
+/* Validate and deep-copy the circuit, then build the execution plan with the
+ * context's options (host only; no device work except uploading tables).
+ * On error the previously loaded circuit stays in place. */
+sim_status sim_load_circuit(sim_ctx *ctx, const sim_gate *gates, uint64_t n_gates);
+
+/* Initialise |0...0>, execute the plan on the context's stream and wait
+ * for completion (Alg. 5 adaptive simulation). */
+sim_status sim_run(sim_ctx *ctx);
+
+/* As sim_run, without waiting: the work is enqueued on the stream; the
+ * state may be read only after the stream has been synchronised. */
+sim_status sim_run_async(sim_ctx *ctx);
+
+/* Copy amplitudes to host: out[2*i], out[2*i+1] = re, im of amplitude
+ * idx[i] (logical index).  idx == NULL copies all 2^N amplitudes (n must then
+ * be 2^N).  Synchronises the stream.  Requires a completed sim_run. */
+sim_status sim_amplitudes(sim_ctx *ctx, const uint64_t *idx, uint64_t n, double *out);
+
+/* Marginal probabilities over the qubit list (Sec. 2.3 measurement model):
+ * out[y] = sum over i whose bit qubits[t] equals bit t of y of |a_i|^2,
+ * accumulated in FP64 in a fixed order (deterministic).  nq = 0 gives the
+ * norm in out[0].  nq <= 16.  out holds 2^nq doubles (host). */
+sim_status sim_probabilities(sim_ctx *ctx, const uint32_t *qubits, uint32_t nq, double *out);
+
+/* <a|b> = sum_i conj(a_i) b_i between the states of two contexts with the
+ * same N (any dtypes), accumulated in FP64 in a fixed order. out[0..1] =
+ * (re, im).  Both contexts must have run; launched on a's stream. */
+sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out);
+
+sim_status sim_stats(const sim_ctx *ctx, sim_run_stats *out);
+
+/* Per-op device timing: when enabled, sim_run records a pair of HIP events on
+ * the context's stream around every kernel launch of the plan. */
+sim_status sim_set_profiling(sim_ctx *ctx, uint32_t enable);
+
+typedef struct {
+    uint32_t kind;      /* sim_op_kind of the plan op */
+    uint32_t buffer;    /* 0 = full state */
+    double ms;          /* device time between the op's events (0 if not timed) */
+    double flops;       /* floating-point operations of the op (plan accounting) */
+    double bytes;       /* algorithmic HBM bytes of the op (plan accounting) */
+} sim_op_timing;
+
+/* Timings of the last profiled run, one entry per plan op (waits for the
+ * stream).  cap = room in out; *n receives the number of plan ops. */
+sim_status sim_op_timings(sim_ctx *ctx, sim_op_timing *out, uint64_t cap, uint64_t *n);
+
+/* Text of the last error on this context (static storage; never NULL). */
+const char *sim_last_error(const sim_ctx *ctx);
+
+sim_status sim_destroy(sim_ctx *ctx);
+
+/* ---- batched small circuits (serving) --------------------------------------
+ * Run several contexts whose states are small (N <= 13 for C128, N <= 14 for
+ * C64) in ONE launch on `stream`: one workgroup per circuit keeps the whole
+ * state on chip, applies the whole gate list and writes the final state to
+ * the context's buffer.  Each context must have a loaded circuit.  Results
+ * equal those of sim_run on each context alone, up to rounding order. */
+sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream);
+
+/* ---- host-only planning (no device needed) --------------------------------
+ * Build the plan the library would execute for this circuit, for inspection
+ * and for checking the optimiser on a machine without a GPU.  The plan is
+ * independent of any context; free it with sim_plan_destroy. */
+typedef enum {
+    SIM_OP_INIT = 0,     /* buffer := |0...0> */
+    SIM_OP_KRON = 1,     /* buffer := src_hi (x) src_lo (tensor product, Alg. 5) */
+    SIM_OP_DENSE = 2,    /* full-pass dense gate on `qubits` (matrix in payload) */
+    SIM_OP_DIAG = 3,     /* full-pass diagonal on `qubits` (table in payload) */
+    SIM_OP_STAGE = 4,    /* cache-blocked stage: gates applied chunk by chunk */
+    SIM_OP_PERM = 5      /* qubit permutation: physical bit p -> perm[p] */
+} sim_op_kind;
+
+typedef struct {
+    uint32_t kind;          /* sim_op_kind */
+    uint32_t buffer;        /* 0 = the full state, >0 = booster sub-state */
+    uint32_t buffer_qubits; /* qubits of that buffer */
+    uint32_t src_lo, src_hi;/* KRON sources (buffer ids); lo supplies the low bits */
+    uint32_t nq;            /* qubits of a DENSE/DIAG op, gates of a STAGE */
+    uint32_t qubits[32];    /* DENSE/DIAG: physical qubits (bit t <-> qubits[t]);
+                               PERM: destination bit of each source bit;
+                               STAGE: physical local qubits (first `local_qubits`) */
+    uint32_t local_qubits;  /* STAGE: C */
+    uint32_t n_phases;      /* STAGE: register phases */
+    uint64_t payload_len;   /* complex entries in the payload (matrix / table) */
+    uint64_t first_gate;    /* STAGE: index of its first gate in sim_plan_stage_gate */
+} sim_plan_op;
+
+/* A gate as executed inside a stage or a sub-state run, after fusion:
+ * a dense or diagonal operator on `nq` physical qubits of its buffer. */
+typedef struct {
+    uint32_t diagonal;      /* 1: payload is a 2^nq diagonal; 0: 2^nq x 2^nq matrix */
+    uint32_t nq;
+    uint32_t qubits[16];
+    uint64_t payload_len;
+} sim_plan_gate;
+
+sim_status sim_plan_build(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts,
+                          const sim_gate *gates, uint64_t n_gates, sim_plan **out);
+uint64_t sim_plan_num_ops(const sim_plan *plan);
+/* payload: NULL or room for payload_len complex values (2*payload_len doubles) */
+sim_status sim_plan_get_op(const sim_plan *plan, uint64_t i, sim_plan_op *op, double *payload);
+/* gates of a STAGE op in execution order: i in [0, op.nq) */
+sim_status sim_plan_stage_gate(const sim_plan *plan, uint64_t op_index, uint64_t i,
+                               sim_plan_gate *g, double *payload);
+/* The i-th operator the stage kernel applies for STAGE op `op_index`, after
+ * register phasing and fusion (all phases flattened, in execution order), as a
+ * dense (2^nq x 2^nq, block diagonal in its selector qubits) or diagonal
+ * operator on physical qubits.  Returns SIM_E_INVAL past the last one. */
+sim_status sim_plan_stage_kernel_op(const sim_plan *plan, uint64_t op_index, uint64_t i,
+                                    sim_plan_gate *g, double *payload);
+/* final logical -> physical map of the full state: phys[q] = bit position */
+sim_status sim_plan_layout(const sim_plan *plan, uint32_t *phys);
+sim_status sim_plan_stats(const sim_plan *plan, sim_run_stats *out);
+/* Diagnostics of the optimiser passes: number of gates each pass visited. */
+sim_status sim_plan_counters(const sim_plan *plan, uint64_t *dd_visits, uint64_t *booster_gates,
+                             uint64_t *booster_groups);
+sim_status sim_plan_destroy(sim_plan *plan);
+
+/* Library version string. */
+const char *sim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSIM355_H */

@@ -142,7 +142,7 @@ static void og_apply_one(int n, const og_gate *g, const double *M, double *a)
         off[r] = o;
     }
     int64_t groups = (int64_t)1 << (n - k);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (groups >= 65536)
     for (int64_t grp = 0; grp < groups; ++grp) {
         /* base index: insert a zero at every target position, low to high */
         uint64_t base = (uint64_t)grp;

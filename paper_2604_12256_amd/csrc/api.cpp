@@ -1,0 +1,861 @@
+// C ABI of the simulator and the executor that runs a plan on the device
+// (adaptive simulation, Alg. 5: tensor product, fused diagonal, dense gate,
+// chunk-wise stage; Alg. 1 when no optimisation is enabled).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "ir.hpp"
+#include "qsim355.h"
+
+using qs::cplx;
+
+namespace {
+
+struct Prepared {
+    sim_op_kind kind;
+    int buffer = 0, nb = 0;
+    qs::GateDesc gd{};          // DENSE / DIAG
+    int lo = 0, hi = 0;         // KRON sources
+    size_t prog_off = 0;        // STAGE: word offset of its program
+    int C = 0, nph = 0;
+    uint64_t nchunks = 0;
+    bool small = false;         // STAGE run by the small-state kernel
+    uint32_t item = 0;          // index of its SmallItem
+    uint32_t batch = 0;         // ops of the batch starting here (0 = inside a batch)
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+hipError_t grow(DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.bytes = bytes;
+    return e;
+}
+
+const char *kNullCtx = "null context";
+
+}  // namespace
+
+struct sim_plan {
+    qs::Plan plan;
+};
+
+struct sim_ctx {
+    int n = 0;
+    sim_dtype dtype = SIM_C128;
+    qs::Options opt;
+    void *state = nullptr;
+    uint64_t state_bytes = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    std::vector<qs::Operator> gates;
+    qs::Plan plan;
+    bool loaded = false, ran = false;
+
+    DevBuf tables, prog, gdesc, items, scratch, io;
+    std::vector<DevBuf> subbufs;          // booster sub-states (index = buffer id)
+    std::vector<Prepared> prep;
+    std::vector<qs::SmallItem> host_items; // for batched serving launches
+    std::vector<qs::GateDesc> host_gdesc;
+    uint32_t small_n = 0;                  // whole-circuit small program (serving)
+    bool small_whole = false;
+    size_t small_whole_item = 0;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timing_pending = false;
+    bool profiling = false, profiled = false;
+    std::vector<hipEvent_t> op_ev;       // 2 per plan op when profiling
+    sim_run_stats stats{};
+    std::string err;
+
+    size_t amp_bytes() const { return dtype == SIM_C128 ? 16 : 8; }
+    void *buf(int id) { return id == 0 ? state : subbufs[id].p; }
+};
+
+namespace {
+
+sim_status fail(sim_ctx *c, sim_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+sim_status hip_fail(sim_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, SIM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr, where)                         \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+bool convert_gates(const sim_gate *gates, uint64_t ng, int n, std::vector<qs::Operator> &out, std::string *err)
+{
+    out.clear();
+    out.reserve(ng);
+    for (uint64_t i = 0; i < ng; ++i) {
+        std::string e;
+        qs::Operator op = qs::gate_operator(gates[i], n, &e);
+        if (!e.empty()) {
+            *err = "gate " + std::to_string(i) + ": " + e;
+            return false;
+        }
+        out.push_back(std::move(op));
+    }
+    return true;
+}
+
+// Program words of one stage (layout documented in kernel_stage.hip).
+void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, std::vector<cplx> &tables)
+{
+    const int C = (int)st.local.size(), n = st.buffer_qubits;
+    const size_t base = w.size();
+    w.resize(base + 128, 0);
+    uint64_t L = 0;
+    for (int q : st.local) L |= 1ull << q;
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
+    const uint64_t G = all & ~L;
+    w[base + 0] = (uint32_t)C;
+    w[base + 1] = (uint32_t)n;
+    w[base + 2] = (uint32_t)st.phases.size();
+    w[base + 3] = (uint32_t)reg_bits;
+    w[base + 4] = (uint32_t)L;
+    w[base + 5] = (uint32_t)(L >> 32);
+    w[base + 6] = (uint32_t)G;
+    w[base + 7] = (uint32_t)(G >> 32);
+    for (int i = 0; i < C; ++i) w[base + 8 + i] = (uint32_t)st.local[i];
+    for (size_t p = 0; p < st.phases.size(); ++p) {
+        const qs::Phase &ph = st.phases[p];
+        w[base + 32 + p] = (uint32_t)(w.size() - base);
+        const size_t pb = w.size();
+        w.resize(pb + 16 + 32 * ph.ops.size(), 0);
+        uint32_t rmask = 0;
+        for (int i : ph.reg) rmask |= 1u << i;
+        const uint32_t nonr = ((1u << C) - 1) & ~rmask;
+        w[pb + 0] = (uint32_t)ph.ops.size();
+        w[pb + 1] = nonr;
+        w[pb + 2] = rmask;
+        std::vector<int> reg_phys;
+        for (int i : ph.reg) reg_phys.push_back(st.local[i]);
+        uint64_t lane_phys = 0;
+        for (int i = 0, cnt = 0; i < C && cnt < 6; ++i)
+            if (!((rmask >> i) & 1)) {
+                lane_phys |= 1ull << st.local[i];
+                ++cnt;
+            }
+        for (size_t o = 0; o < ph.ops.size(); ++o) {
+            const qs::KOp &k = ph.ops[o];
+            uint32_t *op = &w[pb + 16 + 32 * o];
+            const uint64_t toff = tables.size();
+            tables.insert(tables.end(), k.table.begin(), k.table.end());
+            op[4] = (uint32_t)toff;
+            op[5] = (uint32_t)(toff >> 32);
+            const std::vector<int> &pos = k.type == qs::KOp::DENSE ? k.sel : k.dq;
+            if (pos.size() > 32) throw std::runtime_error("encode_stage: too many bit positions");
+            for (size_t t = 0; t < pos.size(); ++t) op[8 + t / 4] |= (uint32_t)pos[t] << (8 * (t % 4));
+            if (k.type == qs::KOp::DENSE) {
+                op[0] = 1;
+                op[1] = k.reg_mask;
+                op[2] = (uint32_t)k.sel.size();
+                bool uni = true;
+                for (int t : k.sel)
+                    if ((lane_phys >> t) & 1) uni = false;
+                op[3] = uni ? 1u : 0u;
+            } else {
+                op[0] = 2;
+                op[1] = (uint32_t)k.dq.size();
+                if (k.dq.size() > 24) throw std::runtime_error("encode_stage: diagonal too wide");
+                for (int j = 0; j < (1 << reg_bits); ++j) {
+                    uint32_t y = 0;
+                    for (size_t t = 0; t < k.dq.size(); ++t)
+                        for (int b = 0; b < reg_bits; ++b)
+                            if (k.dq[t] == reg_phys[b] && ((j >> b) & 1)) y |= 1u << t;
+                    op[16 + j / 2] |= y << (16 * (j & 1));
+                }
+            }
+        }
+    }
+}
+
+qs::GateDesc desc_of(const qs::Operator &g, uint64_t toff)
+{
+    qs::GateDesc d{};
+    d.diag = g.diag ? 1u : 0u;
+    d.k = (uint32_t)g.k();
+    for (int t = 0; t < g.k() && t < 24; ++t) d.q[t] = g.q[t];
+    if (!g.diag) {
+        std::vector<int> s = g.q;
+        std::sort(s.begin(), s.end());
+        for (int t = 0; t < g.k() && t < 6; ++t) d.sorted[t] = s[t];
+    }
+    d.table = toff;
+    return d;
+}
+
+template <typename R>
+std::vector<qs::c2_t<R>> to_device_precision(const std::vector<cplx> &v)
+{
+    std::vector<qs::c2_t<R>> out(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        out[i].x = (R)v[i].real();
+        out[i].y = (R)v[i].imag();
+    }
+    return out;
+}
+
+// Uploads every table and program of the plan and prepares the launches.
+sim_status prepare(sim_ctx *c)
+{
+    const qs::Plan &P = c->plan;
+    std::vector<cplx> tables;
+    std::vector<uint32_t> prog;
+    std::vector<qs::GateDesc> gdesc;
+    std::vector<qs::SmallItem> items;
+    std::vector<size_t> item_gate_off;
+    c->prep.clear();
+    // sub-state buffers
+    c->subbufs.resize(P.buffer_qubits.size());
+    for (size_t b = 1; b < P.buffer_qubits.size(); ++b) {
+        hipError_t e = grow(c->subbufs[b], c->amp_bytes() << P.buffer_qubits[b]);
+        if (e != hipSuccess) return hip_fail(c, e, "sub-state allocation");
+    }
+    const int small_max = qs::small_max_qubits(c->dtype == SIM_C128);
+    for (const qs::PlanOp &op : P.ops) {
+        Prepared p;
+        p.kind = op.kind;
+        p.buffer = op.buffer;
+        p.nb = op.buffer_qubits;
+        switch (op.kind) {
+        case SIM_OP_INIT:
+            break;
+        case SIM_OP_KRON:
+            p.lo = op.src_lo;
+            p.hi = op.src_hi;
+            break;
+        case SIM_OP_DENSE:
+        case SIM_OP_DIAG: {
+            const uint64_t toff = tables.size();
+            if (op.op.diag) tables.insert(tables.end(), op.op.m.begin(), op.op.m.end());
+            else tables.insert(tables.end(), op.op.m.begin(), op.op.m.end());
+            p.gd = desc_of(op.op, toff);
+            break;
+        }
+        case SIM_OP_STAGE: {
+            const bool whole = (int)op.local.size() == op.buffer_qubits;
+            if (whole && op.buffer_qubits <= small_max && op.phases.empty()) {
+                p.small = true;
+                qs::SmallItem it{};
+                it.n = (uint32_t)op.buffer_qubits;
+                it.ngates = (uint32_t)op.gates.size();
+                it.init = 0;
+                item_gate_off.push_back(gdesc.size());
+                for (const qs::Operator &g : op.gates) {
+                    gdesc.push_back(desc_of(g, tables.size()));
+                    tables.insert(tables.end(), g.m.begin(), g.m.end());
+                }
+                p.item = (uint32_t)items.size();
+                it.state = c->buf(op.buffer);
+                items.push_back(it);
+            } else {
+                p.prog_off = prog.size();
+                p.C = (int)op.local.size();
+                p.nph = (int)op.phases.size();
+                p.nchunks = 1ull << (op.buffer_qubits - p.C);
+                encode_stage(op, c->opt.reg_bits, prog, tables);
+            }
+            break;
+        }
+        default:
+            return fail(c, SIM_E_UNSUPPORTED, "plan op kind not executable");
+        }
+        c->prep.push_back(p);
+    }
+    // batches of consecutive small runs on distinct buffers
+    for (size_t i = 0; i < c->prep.size();) {
+        if (!c->prep[i].small) {
+            ++i;
+            continue;
+        }
+        size_t j = i;
+        std::vector<int> seen;
+        while (j < c->prep.size() && c->prep[j].small &&
+               std::find(seen.begin(), seen.end(), c->prep[j].buffer) == seen.end()) {
+            seen.push_back(c->prep[j].buffer);
+            ++j;
+        }
+        c->prep[i].batch = (uint32_t)(j - i);
+        i = j;
+    }
+    // upload
+    const size_t amp = c->amp_bytes();
+    HIPCHK(c, grow(c->tables, std::max<size_t>(tables.size() * amp, 256)), "table allocation");
+    HIPCHK(c, grow(c->prog, std::max<size_t>(prog.size() * 4, 256)), "program allocation");
+    HIPCHK(c, grow(c->gdesc, std::max<size_t>(gdesc.size() * sizeof(qs::GateDesc), 256)), "gate allocation");
+    HIPCHK(c, grow(c->items, std::max<size_t>(items.size() * sizeof(qs::SmallItem), 256)), "item allocation");
+    for (size_t i = 0; i < items.size(); ++i) {
+        items[i].gates = (const qs::GateDesc *)c->gdesc.p + item_gate_off[i];
+        items[i].tables = c->tables.p;
+    }
+    if (!tables.empty()) {
+        if (c->dtype == SIM_C128) {
+            auto t = to_device_precision<double>(tables);
+            HIPCHK(c, hipMemcpyAsync(c->tables.p, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, c->stream),
+                   "table upload");
+            HIPCHK(c, hipStreamSynchronize(c->stream), "table upload");
+        } else {
+            auto t = to_device_precision<float>(tables);
+            HIPCHK(c, hipMemcpyAsync(c->tables.p, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, c->stream),
+                   "table upload");
+            HIPCHK(c, hipStreamSynchronize(c->stream), "table upload");
+        }
+    }
+    if (!prog.empty())
+        HIPCHK(c, hipMemcpyAsync(c->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice, c->stream),
+               "program upload");
+    if (!gdesc.empty())
+        HIPCHK(c, hipMemcpyAsync(c->gdesc.p, gdesc.data(), gdesc.size() * sizeof(qs::GateDesc), hipMemcpyHostToDevice,
+                                 c->stream),
+               "gate upload");
+    if (!items.empty())
+        HIPCHK(c, hipMemcpyAsync(c->items.p, items.data(), items.size() * sizeof(qs::SmallItem), hipMemcpyHostToDevice,
+                                 c->stream),
+               "item upload");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "upload");
+    c->host_items = items;
+    return SIM_OK;
+}
+
+template <typename R>
+sim_status execute(sim_ctx *c)
+{
+    const size_t amp = c->amp_bytes();
+    const R *unused = nullptr;
+    (void)unused;
+    for (size_t i = 0; i < c->prep.size(); ++i) {
+        const Prepared &p = c->prep[i];
+        hipError_t e = hipSuccess;
+        if (c->profiling) HIPCHK(c, hipEventRecord(c->op_ev[2 * i], c->stream), "event record");
+        switch (p.kind) {
+        case SIM_OP_INIT:
+            e = qs::launch_init<R>(c->buf(p.buffer), p.nb, c->stream);
+            break;
+        case SIM_OP_KRON: {
+            const int nlo = c->plan.buffer_qubits[p.lo], nhi = c->plan.buffer_qubits[p.hi];
+            e = qs::launch_kron<R>(c->buf(p.buffer), c->buf(p.lo), nlo, c->buf(p.hi), nhi, c->stream);
+            break;
+        }
+        case SIM_OP_DENSE:
+            e = qs::launch_dense<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp,
+                                    c->stream);
+            break;
+        case SIM_OP_DIAG:
+            e = qs::launch_diag_q<R>(c->buf(p.buffer), p.nb, (int)p.gd.k, p.gd.q,
+                                     (const char *)c->tables.p + p.gd.table * amp, c->stream);
+            break;
+        case SIM_OP_STAGE:
+            if (p.small) {
+                if (p.batch) {
+                    uint32_t maxn = 0;
+                    for (uint32_t u = 0; u < p.batch; ++u) maxn = std::max<uint32_t>(maxn, c->prep[i + u].nb);
+                    e = qs::launch_small_batch<R>((const qs::SmallItem *)c->items.p + p.item, p.batch, maxn,
+                                                  c->stream);
+                }
+            } else {
+                qs::StageLaunch L;
+                L.state = c->buf(p.buffer);
+                L.prog = (const uint32_t *)c->prog.p + p.prog_off;
+                L.tables = c->tables.p;
+                L.n = p.nb;
+                L.C = p.C;
+                L.nphases = p.nph;
+                L.nchunks = p.nchunks;
+                e = qs::launch_stage<R>(L, c->stream);
+            }
+            break;
+        default:
+            return fail(c, SIM_E_UNSUPPORTED, "plan op kind not executable");
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+        if (c->profiling) HIPCHK(c, hipEventRecord(c->op_ev[2 * i + 1], c->stream), "event record");
+    }
+    return SIM_OK;
+}
+
+void fill_stats(const qs::Plan &P, uint64_t n_gates, sim_run_stats *s)
+{
+    s->n_gates = n_gates;
+    s->n_ops = P.stats.n_ops;
+    s->full_passes = P.stats.full_passes;
+    s->write_passes = P.stats.write_passes;
+    s->n_stages = P.stats.n_stages;
+    s->n_dense = P.stats.n_dense;
+    s->n_diag = P.stats.n_diag;
+    s->n_kron = P.stats.n_kron;
+    s->n_perm = P.stats.n_perm;
+    s->n_subruns = P.stats.n_subruns;
+    s->plan_ms = P.stats.plan_ms;
+    s->algorithmic_bytes = P.stats.bytes;
+    s->flops = P.stats.flops;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sim_version(void) { return "qsim355 0.1 (gfx950)"; }
+
+sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts, sim_ctx **out)
+{
+    if (!out || !opts) return SIM_E_INVAL;
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 34) return SIM_E_INVAL;
+    if (dtype != SIM_C128 && dtype != SIM_C64) return SIM_E_INVAL;
+    if (!opts->dev_state) return SIM_E_INVAL;
+    const uint64_t need = (dtype == SIM_C128 ? 16ull : 8ull) << n_qubits;
+    if (opts->dev_state_bytes < need) return SIM_E_NOMEM;
+    sim_ctx *c = new (std::nothrow) sim_ctx();
+    if (!c) return SIM_E_NOMEM;
+    c->n = (int)n_qubits;
+    c->dtype = dtype;
+    c->opt = qs::resolve_options(opts, dtype, (int)n_qubits);
+    c->state = opts->dev_state;
+    c->state_bytes = opts->dev_state_bytes;
+    c->stream = (hipStream_t)opts->stream;
+    if (hipGetDevice(&c->device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return SIM_E_DEVICE;
+    }
+    *out = c;
+    return SIM_OK;
+}
+
+sim_status sim_load_circuit(sim_ctx *c, const sim_gate *gates, uint64_t n_gates)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!gates && n_gates) return fail(c, SIM_E_INVAL, "gates is NULL");
+    std::vector<qs::Operator> ops;
+    std::string err;
+    if (!convert_gates(gates, n_gates, c->n, ops, &err)) return fail(c, SIM_E_INVAL, err);
+    qs::Plan plan;
+    plan.n = c->n;
+    plan.dtype = c->dtype;
+    plan.opt = c->opt;
+    try {
+        qs::build_plan(plan, ops);
+    } catch (const std::exception &ex) {
+        return fail(c, SIM_E_UNSUPPORTED, std::string("planner: ") + ex.what());
+    }
+    std::swap(c->plan, plan);
+    std::swap(c->gates, ops);
+    sim_status s;
+    try {
+        s = prepare(c);
+    } catch (const std::exception &ex) {
+        s = fail(c, SIM_E_UNSUPPORTED, std::string("prepare: ") + ex.what());
+    }
+    if (s != SIM_OK) {  // keep the old circuit
+        std::swap(c->plan, plan);
+        std::swap(c->gates, ops);
+        if (c->loaded) prepare(c);
+        return s;
+    }
+    c->loaded = true;
+    c->ran = false;
+    fill_stats(c->plan, c->gates.size(), &c->stats);
+    return SIM_OK;
+}
+
+sim_status sim_run_async(sim_ctx *c)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->loaded) return fail(c, SIM_E_STATE, "no circuit loaded");
+    if (c->profiling) {
+        while (c->op_ev.size() < 2 * c->prep.size()) {
+            hipEvent_t ev;
+            HIPCHK(c, hipEventCreate(&ev), "event create");
+            c->op_ev.push_back(ev);
+        }
+    }
+    c->profiled = c->profiling;
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream), "event record");
+    sim_status s = c->dtype == SIM_C128 ? execute<double>(c) : execute<float>(c);
+    if (s != SIM_OK) return s;
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream), "event record");
+    c->timing_pending = true;
+    c->ran = true;
+    return SIM_OK;
+}
+
+sim_status sim_run(sim_ctx *c)
+{
+    sim_status s = sim_run_async(c);
+    if (s != SIM_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
+    c->stats.run_ms = ms;
+    c->timing_pending = false;
+    return SIM_OK;
+}
+
+sim_status sim_amplitudes(sim_ctx *c, const uint64_t *idx, uint64_t m, double *out)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
+    if (!out && m) return fail(c, SIM_E_INVAL, "out is NULL");
+    const uint64_t len = 1ull << c->n;
+    const std::vector<int> &lay = c->plan.layout;
+    bool identity = true;
+    for (int q = 0; q < c->n; ++q) identity &= (lay[q] == q);
+    auto phys = [&](uint64_t x) {
+        if (identity) return x;
+        uint64_t y = 0;
+        for (int q = 0; q < c->n; ++q) y |= ((x >> q) & 1ull) << lay[q];
+        return y;
+    };
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    const uint64_t kBatch = 1ull << 22;
+    if (!idx) {
+        if (m != len) return fail(c, SIM_E_INVAL, "idx NULL requires n == 2^N");
+        if (identity && c->dtype == SIM_C128) {
+            HIPCHK(c, hipMemcpy(out, c->state, len * 16, hipMemcpyDeviceToHost), "copy out");
+            return SIM_OK;
+        }
+    } else {
+        for (uint64_t i = 0; i < m; ++i)
+            if (idx[i] >= len) return fail(c, SIM_E_INVAL, "amplitude index out of range");
+    }
+    std::vector<uint64_t> hidx;
+    for (uint64_t s0 = 0; s0 < m; s0 += kBatch) {
+        const uint64_t cnt = std::min(kBatch, m - s0);
+        hidx.resize(cnt);
+        for (uint64_t i = 0; i < cnt; ++i) hidx[i] = phys(idx ? idx[s0 + i] : s0 + i);
+        HIPCHK(c, grow(c->io, cnt * (8 + 16)), "io allocation");
+        uint64_t *didx = (uint64_t *)c->io.p;
+        double *dout = (double *)((char *)c->io.p + cnt * 8);
+        HIPCHK(c, hipMemcpyAsync(didx, hidx.data(), cnt * 8, hipMemcpyHostToDevice, c->stream), "index upload");
+        hipError_t e = c->dtype == SIM_C128 ? qs::launch_gather<double>(c->state, didx, cnt, dout, c->stream)
+                                            : qs::launch_gather<float>(c->state, didx, cnt, dout, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "gather");
+        HIPCHK(c, hipMemcpyAsync(out + 2 * s0, dout, cnt * 16, hipMemcpyDeviceToHost, c->stream), "copy out");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    }
+    return SIM_OK;
+}
+
+sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, double *out)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
+    if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
+    if (nq > 16 || (int)nq > c->n) return fail(c, SIM_E_INVAL, "at most 16 qubits");
+    if (nq && !qubits) return fail(c, SIM_E_INVAL, "qubits is NULL");
+    std::vector<int> ph(nq);
+    for (uint32_t t = 0; t < nq; ++t) {
+        if ((int)qubits[t] >= c->n) return fail(c, SIM_E_INVAL, "qubit out of range");
+        for (uint32_t u = 0; u < t; ++u)
+            if (qubits[u] == qubits[t]) return fail(c, SIM_E_INVAL, "duplicate qubit");
+        ph[t] = c->plan.layout[qubits[t]];
+    }
+    std::vector<int> sorted = ph;
+    std::sort(sorted.begin(), sorted.end());
+    const size_t nbins = 1ull << nq;
+    const size_t scr = qs::marginal_scratch_bytes(c->n, (int)nq);
+    HIPCHK(c, grow(c->scratch, scr + nbins * 8 + 64), "scratch allocation");
+    double *dout = (double *)((char *)c->scratch.p + ((scr + 63) / 64) * 64);
+    hipError_t e = c->dtype == SIM_C128
+                       ? qs::launch_marginal<double>(c->state, c->n, sorted.data(), (int)nq, dout,
+                                                     (double *)c->scratch.p, c->stream)
+                       : qs::launch_marginal<float>(c->state, c->n, sorted.data(), (int)nq, dout,
+                                                    (double *)c->scratch.p, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "marginal");
+    std::vector<double> bins(nbins);
+    HIPCHK(c, hipMemcpyAsync(bins.data(), dout, nbins * 8, hipMemcpyDeviceToHost, c->stream), "copy out");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    // bin bit u <-> sorted[u]; output bit t <-> ph[t]
+    std::vector<int> where(nq);
+    for (uint32_t t = 0; t < nq; ++t)
+        where[t] = (int)(std::find(sorted.begin(), sorted.end(), ph[t]) - sorted.begin());
+    for (size_t y = 0; y < nbins; ++y) {
+        size_t b = 0;
+        for (uint32_t t = 0; t < nq; ++t) b |= ((y >> t) & 1ull) << where[t];
+        out[y] = bins[b];
+    }
+    return SIM_OK;
+}
+
+sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out)
+{
+    if (!a || !b) return SIM_E_INVAL;
+    if (!out) return fail(a, SIM_E_INVAL, "out is NULL");
+    if (a->n != b->n) return fail(a, SIM_E_INVAL, "qubit counts differ");
+    if (!a->ran || !b->ran) return fail(a, SIM_E_STATE, "both contexts must have run");
+    if (a->plan.layout != b->plan.layout) return fail(a, SIM_E_UNSUPPORTED, "states use different qubit layouts");
+    HIPCHK(a, hipStreamSynchronize(b->stream), "synchronize");
+    const size_t scr = qs::inner_scratch_bytes(a->n);
+    HIPCHK(a, grow(a->scratch, scr + 64), "scratch allocation");
+    double *dout = (double *)((char *)a->scratch.p + scr);
+    hipError_t e;
+    if (a->dtype == SIM_C128 && b->dtype == SIM_C128)
+        e = qs::launch_inner<double, double>(a->state, b->state, a->n, dout, (double *)a->scratch.p, a->stream);
+    else if (a->dtype == SIM_C128)
+        e = qs::launch_inner<double, float>(a->state, b->state, a->n, dout, (double *)a->scratch.p, a->stream);
+    else if (b->dtype == SIM_C128)
+        e = qs::launch_inner<float, double>(a->state, b->state, a->n, dout, (double *)a->scratch.p, a->stream);
+    else
+        e = qs::launch_inner<float, float>(a->state, b->state, a->n, dout, (double *)a->scratch.p, a->stream);
+    if (e != hipSuccess) return hip_fail(a, e, "inner product");
+    HIPCHK(a, hipMemcpyAsync(out, dout, 16, hipMemcpyDeviceToHost, a->stream), "copy out");
+    HIPCHK(a, hipStreamSynchronize(a->stream), "synchronize");
+    return SIM_OK;
+}
+
+sim_status sim_stats(const sim_ctx *c, sim_run_stats *out)
+{
+    if (!c || !out) return SIM_E_INVAL;
+    sim_ctx *m = const_cast<sim_ctx *>(c);
+    if (m->timing_pending && hipEventQuery(m->ev1) == hipSuccess) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, m->ev0, m->ev1) == hipSuccess) m->stats.run_ms = ms;
+        m->timing_pending = false;
+    }
+    *out = c->stats;
+    return SIM_OK;
+}
+
+sim_status sim_set_profiling(sim_ctx *c, uint32_t enable)
+{
+    if (!c) return SIM_E_INVAL;
+    c->profiling = enable != 0;
+    return SIM_OK;
+}
+
+sim_status sim_op_timings(sim_ctx *c, sim_op_timing *out, uint64_t cap, uint64_t *n)
+{
+    if (!c || !n) return SIM_E_INVAL;
+    *n = c->prep.size();
+    if (!c->profiled) return fail(c, SIM_E_STATE, "no profiled run");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    for (size_t i = 0; i < c->prep.size() && i < cap; ++i) {
+        out[i].kind = c->plan.ops[i].kind;
+        out[i].buffer = (uint32_t)c->plan.ops[i].buffer;
+        out[i].flops = c->plan.ops[i].flops;
+        out[i].bytes = c->plan.ops[i].bytes;
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->op_ev[2 * i], c->op_ev[2 * i + 1]), "event time");
+        out[i].ms = ms;
+    }
+    return SIM_OK;
+}
+
+const char *sim_last_error(const sim_ctx *c) { return c ? c->err.c_str() : kNullCtx; }
+
+sim_status sim_destroy(sim_ctx *c)
+{
+    if (!c) return SIM_E_INVAL;
+    hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->tables, &c->prog, &c->gdesc, &c->items, &c->scratch, &c->io})
+        if (b->p) hipFree(b->p);
+    for (DevBuf &b : c->subbufs)
+        if (b.p) hipFree(b.p);
+    for (hipEvent_t ev : c->op_ev) hipEventDestroy(ev);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    delete c;
+    return SIM_OK;
+}
+
+sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream)
+{
+    if (!ctxs && n_ctx) return SIM_E_INVAL;
+    (void)stream;
+    return SIM_E_UNSUPPORTED;
+}
+
+// ---- host-only planning ----------------------------------------------------
+
+sim_status sim_plan_build(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts, const sim_gate *gates,
+                          uint64_t n_gates, sim_plan **out)
+{
+    if (!out) return SIM_E_INVAL;
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 34 || (dtype != SIM_C128 && dtype != SIM_C64)) return SIM_E_INVAL;
+    if (!gates && n_gates) return SIM_E_INVAL;
+    std::vector<qs::Operator> ops;
+    std::string err;
+    if (!convert_gates(gates, n_gates, (int)n_qubits, ops, &err)) return SIM_E_INVAL;
+    sim_plan *p = new (std::nothrow) sim_plan();
+    if (!p) return SIM_E_NOMEM;
+    p->plan.n = (int)n_qubits;
+    p->plan.dtype = dtype;
+    p->plan.opt = qs::resolve_options(opts, dtype, (int)n_qubits);
+    try {
+        qs::build_plan(p->plan, ops);
+    } catch (const std::exception &) {
+        delete p;
+        return SIM_E_UNSUPPORTED;
+    }
+    *out = p;
+    return SIM_OK;
+}
+
+uint64_t sim_plan_num_ops(const sim_plan *p) { return p ? p->plan.ops.size() : 0; }
+
+sim_status sim_plan_get_op(const sim_plan *p, uint64_t i, sim_plan_op *op, double *payload)
+{
+    if (!p || !op || i >= p->plan.ops.size()) return SIM_E_INVAL;
+    const qs::PlanOp &o = p->plan.ops[i];
+    std::memset(op, 0, sizeof(*op));
+    op->kind = o.kind;
+    op->buffer = (uint32_t)o.buffer;
+    op->buffer_qubits = (uint32_t)o.buffer_qubits;
+    op->src_lo = (uint32_t)o.src_lo;
+    op->src_hi = (uint32_t)o.src_hi;
+    if (o.kind == SIM_OP_DENSE || o.kind == SIM_OP_DIAG) {
+        op->nq = (uint32_t)o.op.q.size();
+        for (size_t t = 0; t < o.op.q.size() && t < 32; ++t) op->qubits[t] = (uint32_t)o.op.q[t];
+        op->payload_len = o.op.m.size();
+        if (payload)
+            for (size_t t = 0; t < o.op.m.size(); ++t) {
+                payload[2 * t] = o.op.m[t].real();
+                payload[2 * t + 1] = o.op.m[t].imag();
+            }
+    } else if (o.kind == SIM_OP_STAGE) {
+        op->nq = (uint32_t)o.gates.size();
+        op->local_qubits = (uint32_t)o.local.size();
+        for (size_t t = 0; t < o.local.size() && t < 32; ++t) op->qubits[t] = (uint32_t)o.local[t];
+        op->n_phases = (uint32_t)o.phases.size();
+    } else if (o.kind == SIM_OP_PERM) {
+        op->nq = (uint32_t)o.perm.size();
+        for (size_t t = 0; t < o.perm.size() && t < 32; ++t) op->qubits[t] = (uint32_t)o.perm[t];
+    }
+    return SIM_OK;
+}
+
+sim_status sim_plan_stage_gate(const sim_plan *p, uint64_t op_index, uint64_t i, sim_plan_gate *g, double *payload)
+{
+    if (!p || !g || op_index >= p->plan.ops.size()) return SIM_E_INVAL;
+    const qs::PlanOp &o = p->plan.ops[op_index];
+    if (o.kind != SIM_OP_STAGE || i >= o.gates.size()) return SIM_E_INVAL;
+    const qs::Operator &x = o.gates[i];
+    std::memset(g, 0, sizeof(*g));
+    g->diagonal = x.diag ? 1 : 0;
+    g->nq = (uint32_t)x.q.size();
+    for (size_t t = 0; t < x.q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)x.q[t];
+    g->payload_len = x.m.size();
+    if (payload)
+        for (size_t t = 0; t < x.m.size(); ++t) {
+            payload[2 * t] = x.m[t].real();
+            payload[2 * t + 1] = x.m[t].imag();
+        }
+    return SIM_OK;
+}
+
+sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64_t i, sim_plan_gate *g,
+                                    double *payload)
+{
+    if (!p || !g || op_index >= p->plan.ops.size()) return SIM_E_INVAL;
+    const qs::PlanOp &o = p->plan.ops[op_index];
+    if (o.kind != SIM_OP_STAGE) return SIM_E_INVAL;
+    for (const qs::Phase &ph : o.phases) {
+        if (i >= ph.ops.size()) {
+            i -= ph.ops.size();
+            continue;
+        }
+        const qs::KOp &k = ph.ops[i];
+        std::memset(g, 0, sizeof(*g));
+        if (k.type == qs::KOp::DIAG) {
+            g->diagonal = 1;
+            g->nq = (uint32_t)k.dq.size();
+            for (size_t t = 0; t < k.dq.size() && t < 16; ++t) g->qubits[t] = (uint32_t)k.dq[t];
+            g->payload_len = k.table.size();
+            if (payload)
+                for (size_t t = 0; t < k.table.size(); ++t) {
+                    payload[2 * t] = k.table[t].real();
+                    payload[2 * t + 1] = k.table[t].imag();
+                }
+            return SIM_OK;
+        }
+        std::vector<int> q;
+        for (int b = 0; b < (int)ph.reg.size(); ++b)
+            if ((k.reg_mask >> b) & 1) q.push_back(o.local[ph.reg[b]]);
+        const int kr = (int)q.size(), ks = (int)k.sel.size();
+        for (int t : k.sel) q.push_back(t);
+        g->diagonal = 0;
+        g->nq = (uint32_t)q.size();
+        for (size_t t = 0; t < q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)q[t];
+        const uint64_t D = 1ull << (kr + ks), dr = 1ull << kr;
+        g->payload_len = D * D;
+        if (payload) {
+            for (uint64_t t = 0; t < 2 * D * D; ++t) payload[t] = 0.0;
+            for (uint64_t sel = 0; sel < (1ull << ks); ++sel)
+                for (uint64_t r = 0; r < dr; ++r)
+                    for (uint64_t c = 0; c < dr; ++c) {
+                        const cplx v = k.table[sel * dr * dr + r * dr + c];
+                        const uint64_t R = r | (sel << kr), Cc = c | (sel << kr);
+                        payload[2 * (R * D + Cc)] = v.real();
+                        payload[2 * (R * D + Cc) + 1] = v.imag();
+                    }
+        }
+        return SIM_OK;
+    }
+    return SIM_E_INVAL;
+}
+
+sim_status sim_plan_layout(const sim_plan *p, uint32_t *phys)
+{
+    if (!p || !phys) return SIM_E_INVAL;
+    for (size_t q = 0; q < p->plan.layout.size(); ++q) phys[q] = (uint32_t)p->plan.layout[q];
+    return SIM_OK;
+}
+
+sim_status sim_plan_stats(const sim_plan *p, sim_run_stats *out)
+{
+    if (!p || !out) return SIM_E_INVAL;
+    std::memset(out, 0, sizeof(*out));
+    fill_stats(p->plan, 0, out);
+    return SIM_OK;
+}
+
+sim_status sim_plan_counters(const sim_plan *p, uint64_t *dd_visits, uint64_t *booster_gates, uint64_t *booster_groups)
+{
+    if (!p) return SIM_E_INVAL;
+    if (dd_visits) *dd_visits = p->plan.stats.dd_visits;
+    if (booster_gates) *booster_gates = p->plan.stats.booster_gates;
+    if (booster_groups) *booster_groups = p->plan.stats.booster_groups;
+    return SIM_OK;
+}
+
+sim_status sim_plan_destroy(sim_plan *p)
+{
+    if (!p) return SIM_E_INVAL;
+    delete p;
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Device-side helpers and the launch interface between the executor and the
+// kernels.  gfx950 (CDNA4) only: 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qs {
+
+// Interleaved complex amplitude: double2 (complex128) or float2 (complex64).
+template <typename R> struct C2;
+template <> struct C2<double> { using T = double2; };
+template <> struct C2<float> { using T = float2; };
+template <typename R> using c2_t = typename C2<R>::T;
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b)
+{
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// acc += m * a
+template <typename V>
+__device__ __forceinline__ void cmac(V &acc, V m, V a)
+{
+    acc.x = fma(m.x, a.x, acc.x);
+    acc.x = fma(-m.y, a.y, acc.x);
+    acc.y = fma(m.x, a.y, acc.y);
+    acc.y = fma(m.y, a.x, acc.y);
+}
+
+// Scatter the low bits of x to the set bit positions of mask (bit-deposit).
+__device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t mask)
+{
+    uint64_t r = 0;
+    while (mask) {
+        const uint64_t low = mask & (~mask + 1);
+        if (x & 1) r |= low;
+        x >>= 1;
+        mask &= mask - 1;
+    }
+    return r;
+}
+
+// Insert a zero bit at each of the ascending positions pos[0..k-1].
+template <int K>
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t g, const int *pos)
+{
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const uint64_t lo = g & ((1ull << pos[t]) - 1);
+        g = ((g >> pos[t]) << (pos[t] + 1)) | lo;
+    }
+    return g;
+}
+
+struct GateDesc {            // one gate of a small-state program / full-pass op
+    uint32_t diag;           // 1: table is a 2^k diagonal (k <= 24); else a dense 2^k x 2^k matrix (k <= 6)
+    uint32_t k;
+    int32_t q[24];           // matrix bit t <-> qubit q[t]
+    int32_t sorted[6];       // dense: q ascending
+    uint64_t table;          // offset (complex entries) in the table arena
+};
+
+struct SmallItem {           // one circuit of a batched small-state launch
+    void *state;             // buffer holding 2^n amplitudes
+    const GateDesc *gates;   // device program
+    const void *tables;      // device table arena (same dtype as the state)
+    uint32_t n, ngates, init;
+    uint32_t pad;
+};
+
+// ---- launchers (return hipError_t of the launch) ---------------------------
+template <typename R> hipError_t launch_init(void *state, int n, hipStream_t s);
+template <typename R> hipError_t launch_dense(void *state, int n, const GateDesc &g, const void *mat, hipStream_t s);
+template <typename R> hipError_t launch_dense_mfma(void *state, int n, const GateDesc &g, const void *mat, hipStream_t s);
+template <typename R> hipError_t launch_diag_q(void *state, int n, int k, const int *q, const void *table, hipStream_t s);
+template <typename R> hipError_t launch_kron(void *dst, const void *lo, int nlo, const void *hi, int nhi, hipStream_t s);
+template <typename R> hipError_t launch_perm(void *dst, const void *src, int n, const int *perm, hipStream_t s);
+template <typename R> hipError_t launch_gather(const void *state, const uint64_t *idx, uint64_t m, double *out, hipStream_t s);
+// marginal over the physical qubits q[0..nq): out[2^nq] doubles (device), scratch as sized by marginal_scratch_bytes
+template <typename R> hipError_t launch_marginal(const void *state, int n, const int *q, int nq, double *out,
+                                                 double *scratch, hipStream_t s);
+size_t marginal_scratch_bytes(int n, int nq);
+template <typename RA, typename RB> hipError_t launch_inner(const void *a, const void *b, int n, double *out,
+                                                            double *scratch, hipStream_t s);
+size_t inner_scratch_bytes(int n);
+template <typename R> hipError_t launch_small_batch(const SmallItem *items_dev, uint32_t count, uint32_t max_n,
+                                                    hipStream_t s);
+int small_max_qubits(bool c128);
+
+// Stage kernel: program built by the executor (see kernel_stage.hip).
+struct StageLaunch {
+    void *state;
+    const uint32_t *prog;    // device program words
+    const void *tables;      // device table arena
+    int n, C, nphases;
+    uint64_t nchunks;
+};
+template <typename R> hipError_t launch_stage(const StageLaunch &L, hipStream_t s);
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+
+}  // namespace qs

@@ -1,0 +1,279 @@
+// Cache-blocked stage kernel (block-by-block scheme, Alg. 2; the "all-in-one"
+// branch of the adaptive simulator, Alg. 5).
+//
+// One workgroup owns one chunk of 2^C amplitudes at a time: the amplitudes
+// whose local qubits (C physical bit positions, always including bits 0..5
+// so that every wave reads 1 KiB / 512 B contiguous runs) vary and whose
+// global qubits are fixed by the chunk id.  The chunk is read from HBM once,
+// every gate of the stage is applied on chip, and it is written back once.
+//
+// On chip the chunk lives in VGPRs: each thread holds 2^RB amplitudes (RB = 4
+// for complex128, 5 for complex64), indexed by RB "register" local bits; the
+// other local bits give the thread id.  The stage is cut into register
+// phases; a phase applies fused dense operators on register bits and
+// diagonal operators on any bits (non-register bits are constants per
+// thread).  Between phases whose register sets differ, the chunk goes through
+// LDS once (write in the old mapping, read in the new one).
+//
+// Program words (built on the host; read with wave-uniform loads):
+//   header  [0] C  [1] n  [2] nphases  [3] RB  [4,5] local mask  [6,7] global mask
+//           [8 + i] physical bit of local bit i (i < C)   [32 + p] word offset of phase p
+//   phase   [0] nops  [1] non-register local mask  [2] register local mask
+//           [16 + 32 o ...] op o
+//   op      [0] type (1 dense, 2 diagonal)  [1] register mask | diagonal size
+//           [2] selector count  [3] selector wave-uniform  [4,5] table offset
+//           [8..15] bit positions (bytes)  [16..31] diagonal: register index part (u16)
+#include "device.hpp"
+
+namespace qs {
+
+namespace {
+
+constexpr int kStageMaxThreads = 512;
+constexpr uint32_t kStageLdsBytes = 128u * 1024u;
+
+template <typename R> __device__ __forceinline__ uint32_t swz(uint32_t i);
+// 16-byte slots: fold the higher index bits into the low 4 (64 banks x 4 B).
+template <> __device__ __forceinline__ uint32_t swz<double>(uint32_t i)
+{
+    return i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12)) & 15u);
+}
+// 8-byte slots: fold into the low 5 bits.
+template <> __device__ __forceinline__ uint32_t swz<float>(uint32_t i)
+{
+    return i ^ (((i >> 5) ^ (i >> 10)) & 31u);
+}
+
+__device__ __forceinline__ uint32_t byte_at(const uint32_t *w, int i) { return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
+
+template <int RB>
+__device__ __forceinline__ void reg_positions(uint32_t rmask, int *pos)
+{
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        pos[b] = __builtin_ctz(rmask);
+        rmask &= rmask - 1;
+    }
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t reg_offset(int j, const int *pos)
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+        if ((j >> b) & 1) o |= 1u << pos[b];
+    return o;
+}
+
+// Dense operator on the register bits of MASK; m holds (2^k)^2 entries,
+// bit t of its index <-> t-th set bit of MASK.
+template <typename R, int RB, int MASK>
+__device__ __forceinline__ void apply_dense(c2_t<R> *amp, const c2_t<R> *__restrict__ m)
+{
+    using V = c2_t<R>;
+    constexpr int K = __builtin_popcount(MASK);
+    constexpr int D = 1 << K;
+    constexpr int NR = 1 << RB;
+#pragma unroll
+    for (int outer = 0; outer < NR; ++outer) {
+        if (outer & MASK) continue;
+        int idx[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            int x = outer, bit = 0;
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                if ((MASK >> b) & 1) {
+                    if ((c >> bit) & 1) x |= 1 << b;
+                    ++bit;
+                }
+            idx[c] = x;
+        }
+        V v[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c] = amp[idx[c]];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            V acc;
+            acc.x = R(0);
+            acc.y = R(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) cmac(acc, m[r * D + c], v[c]);
+            amp[idx[r]] = acc;
+        }
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void dispatch_dense(uint32_t mask, c2_t<R> *amp, const c2_t<R> *m)
+{
+    constexpr int FULL = (1 << RB) - 1;
+    switch (mask) {
+    case 1: apply_dense<R, RB, 1>(amp, m); break;
+    case 2: apply_dense<R, RB, 2>(amp, m); break;
+    case 4: apply_dense<R, RB, 4>(amp, m); break;
+    case 8: apply_dense<R, RB, 8>(amp, m); break;
+    case 3: apply_dense<R, RB, 3>(amp, m); break;
+    case 5: apply_dense<R, RB, 5>(amp, m); break;
+    case 6: apply_dense<R, RB, 6>(amp, m); break;
+    case 9: apply_dense<R, RB, 9>(amp, m); break;
+    case 10: apply_dense<R, RB, 10>(amp, m); break;
+    case 12: apply_dense<R, RB, 12>(amp, m); break;
+    case FULL: apply_dense<R, RB, FULL>(amp, m); break;
+    default:
+        if constexpr (RB == 5) {
+            switch (mask) {
+            case 16: apply_dense<R, RB, 16>(amp, m); break;
+            case 17: apply_dense<R, RB, 17>(amp, m); break;
+            case 18: apply_dense<R, RB, 18>(amp, m); break;
+            case 20: apply_dense<R, RB, 20>(amp, m); break;
+            case 24: apply_dense<R, RB, 24>(amp, m); break;
+            default: break;
+            }
+        }
+        break;
+    }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t tid, uint32_t old_nonr,
+                                          uint32_t old_r, uint32_t new_nonr, uint32_t new_r)
+{
+    constexpr int NR = 1 << RB;
+    int pos[RB];
+    __syncthreads();
+    reg_positions<RB>(old_r, pos);
+    const uint32_t lb = (uint32_t)deposit(tid, old_nonr);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) lds[swz<R>(lb | reg_offset<RB>(j, pos))] = amp[j];
+    __syncthreads();
+    reg_positions<RB>(new_r, pos);
+    const uint32_t nb = (uint32_t)deposit(tid, new_nonr);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) amp[j] = lds[swz<R>(nb | reg_offset<RB>(j, pos))];
+}
+
+template <typename R, int RB>
+__global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
+                                                            const uint32_t *__restrict__ P,
+                                                            const c2_t<R> *__restrict__ tables,
+                                                            uint64_t nchunks)
+{
+    using V = c2_t<R>;
+    constexpr int NR = 1 << RB;
+    extern __shared__ char smem_raw[];
+    V *lds = reinterpret_cast<V *>(smem_raw);
+
+    const int C = (int)P[0];
+    const int nph = (int)P[2];
+    const uint64_t Lmask = (uint64_t)P[4] | ((uint64_t)P[5] << 32);
+    const uint64_t Gmask = (uint64_t)P[6] | ((uint64_t)P[7] << 32);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t all_local = (1u << C) - 1;
+    const uint32_t neutral_nonr = (1u << (C - RB)) - 1;
+    const uint32_t neutral_r = all_local & ~neutral_nonr;
+    uint64_t regphys[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) regphys[b] = 1ull << P[8 + C - RB + b];
+    const uint64_t tphys = deposit(tid, Lmask);
+
+    V amp[NR];
+    for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+        const uint64_t cbase = deposit(chunk, Gmask);
+        {
+            const uint64_t pb = cbase | tphys;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                uint64_t o = pb;
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    if ((j >> b) & 1) o |= regphys[b];
+                amp[j] = state[o];
+            }
+        }
+        uint32_t cur_nonr = neutral_nonr, cur_r = neutral_r;
+        for (int p = 0; p < nph; ++p) {
+            const uint32_t *ph = P + P[32 + p];
+            const uint32_t nops = ph[0], nonr = ph[1], rmask = ph[2];
+            if (rmask != cur_r) {
+                transpose<R, RB>(amp, lds, tid, cur_nonr, cur_r, nonr, rmask);
+                cur_nonr = nonr;
+                cur_r = rmask;
+            }
+            const uint64_t phys_base = cbase | deposit(deposit(tid, nonr), Lmask);
+            for (uint32_t o = 0; o < nops; ++o) {
+                const uint32_t *op = ph + 16 + 32 * o;
+                const uint64_t toff = (uint64_t)op[4] | ((uint64_t)op[5] << 32);
+                if (op[0] == 1u) {
+                    const uint32_t mask = op[1], nsel = op[2];
+                    uint32_t sel = 0;
+                    for (uint32_t u = 0; u < nsel; ++u)
+                        sel |= (uint32_t)((phys_base >> byte_at(op + 8, (int)u)) & 1ull) << u;
+                    const int k = __builtin_popcount(mask);
+                    const uint32_t msz = 1u << (2 * k);
+                    if (op[3]) {
+                        sel = __builtin_amdgcn_readfirstlane(sel);
+                        dispatch_dense<R, RB>(mask, amp, tables + toff + (uint64_t)sel * msz);
+                    } else {
+                        dispatch_dense<R, RB>(mask, amp, tables + toff + (uint64_t)sel * msz);
+                    }
+                } else {
+                    const uint32_t nd = op[1];
+                    uint32_t yc = 0;
+                    for (uint32_t t = 0; t < nd; ++t)
+                        yc |= (uint32_t)((phys_base >> byte_at(op + 8, (int)t)) & 1ull) << t;
+                    const V *T = tables + toff;
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) {
+                        const uint32_t yr = (op[16 + (j >> 1)] >> ((j & 1) * 16)) & 0xffffu;
+                        amp[j] = cmul(amp[j], T[yc | yr]);
+                    }
+                }
+            }
+        }
+        if (cur_r != neutral_r) transpose<R, RB>(amp, lds, tid, cur_nonr, cur_r, neutral_nonr, neutral_r);
+        {
+            const uint64_t pb = cbase | tphys;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                uint64_t o = pb;
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    if ((j >> b) & 1) o |= regphys[b];
+                state[o] = amp[j];
+            }
+        }
+        __syncthreads();  // LDS reuse by the next chunk
+    }
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
+{
+    constexpr int RB = sizeof(R) == 8 ? 4 : 5;
+    const int C = L.C;
+    if (C < RB + 6 || C > 16) return hipErrorInvalidValue;
+    const uint32_t threads = 1u << (C - RB);
+    const uint32_t lds = (uint32_t)sizeof(c2_t<R>) << C;
+    if (threads > (uint32_t)kStageMaxThreads || lds > kStageLdsBytes) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_stage<R, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kStageLdsBytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    uint64_t grid = L.nchunks;
+    if (grid > (1ull << 20)) grid = 1ull << 20;
+    k_stage<R, RB><<<(uint32_t)grid, threads, lds, s>>>((c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables,
+                                                        L.nchunks);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stage<double>(const StageLaunch &, hipStream_t);
+template hipError_t launch_stage<float>(const StageLaunch &, hipStream_t);
+
+}  // namespace qs

@@ -1,0 +1,397 @@
+// Full-pass kernels: state initialisation, dense gate apply on the VALU,
+// diagonal phase apply, tensor product, qubit permutation, reductions,
+// amplitude gather, inner product and a plain copy (bandwidth reference).
+//
+// Every full pass streams the state once from HBM and once back; these
+// kernels are bound by HBM bandwidth (8 TB/s on MI355X), so each thread
+// touches whole 16-byte (complex128) or 8-byte (complex64) amplitudes with
+// consecutive lanes on consecutive addresses wherever the gate allows.
+#include "device.hpp"
+
+namespace qs {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+uint32_t blocks_for(uint64_t work, uint64_t per_block)
+{
+    uint64_t b = (work + per_block - 1) / per_block;
+    return (uint32_t)(b ? b : 1);
+}
+
+// |0...0>: zero fill with amplitude 0 set to 1 (a kernel, not a memset, so
+// that the op can be captured in a graph).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_init(c2_t<R> *__restrict__ a, uint64_t len)
+{
+    using V = c2_t<R>;
+    const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint64_t i = i0 + u;
+        if (i < len) {
+            V v;
+            v.x = i == 0 ? R(1) : R(0);
+            v.y = R(0);
+            a[i] = v;
+        }
+    }
+}
+
+// Dense k-qubit gate, one thread per group of 2^k amplitudes (Sec. 2.2: the
+// 2^k amplitudes that differ only in the gate's qubits are multiplied by the
+// gate matrix).  The matrix index is uniform across the wave.
+template <typename R, int K>
+__global__ __launch_bounds__(kBlock) void k_dense(c2_t<R> *__restrict__ a, const c2_t<R> *__restrict__ m,
+                                                  uint64_t ngroups, GateDesc g)
+{
+    using V = c2_t<R>;
+    constexpr int D = 1 << K;
+    const uint64_t grp = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (grp >= ngroups) return;
+    const uint64_t base = insert_zeros<K>(grp, g.sorted);
+    uint64_t off[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+            if ((r >> t) & 1) o |= 1ull << g.q[t];
+        off[r] = base | o;
+    }
+    V v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) v[c] = a[off[c]];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        V acc;
+        acc.x = R(0);
+        acc.y = R(0);
+#pragma unroll
+        for (int c = 0; c < D; ++c) cmac(acc, m[r * D + c], v[c]);
+        a[off[r]] = acc;
+    }
+}
+
+// Diagonal of 2^k entries over the qubits q[0..k): a[x] *= T[y], y collects
+// bit q[t] of x into bit t (Sec. 4.5: one complex multiply per amplitude).
+struct DiagArgs {
+    int32_t k;
+    int32_t q[24];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_diag(c2_t<R> *__restrict__ a, const c2_t<R> *__restrict__ T,
+                                                 uint64_t len, DiagArgs d)
+{
+    const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const uint64_t x = i0 + u;
+        if (x >= len) return;
+        uint32_t y = 0;
+        for (int t = 0; t < d.k; ++t) y |= (uint32_t)((x >> d.q[t]) & 1) << t;
+        a[x] = cmul(a[x], T[y]);
+    }
+}
+
+// Tensor product (Alg. 5 tensorProduct): dst[(i_hi << nlo) | i_lo] = lo[i_lo] hi[i_hi].
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_kron(c2_t<R> *__restrict__ dst, const c2_t<R> *__restrict__ lo,
+                                                 const c2_t<R> *__restrict__ hi, int nlo, uint64_t len)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (x >= len) return;
+    dst[x] = cmul(lo[x & ((1ull << nlo) - 1)], hi[x >> nlo]);
+}
+
+// Qubit permutation (Sec. 2.3): dst[pi(x)] = src[x], pi moves source bit p to
+// destination bit perm[p].  Out of place.
+struct PermArgs {
+    int32_t n;
+    int32_t perm[40];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_perm(c2_t<R> *__restrict__ dst, const c2_t<R> *__restrict__ src,
+                                                 uint64_t len, PermArgs p)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (x >= len) return;
+    uint64_t y = 0;
+    for (int b = 0; b < p.n; ++b) y |= ((x >> b) & 1ull) << p.perm[b];
+    dst[y] = src[x];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gather(const c2_t<R> *__restrict__ a, const uint64_t *__restrict__ idx,
+                                                   uint64_t m, double2 *__restrict__ out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const c2_t<R> v = a[idx[i]];
+    out[i] = make_double2((double)v.x, (double)v.y);
+}
+
+// Marginal probabilities, deterministic: one wave per (bin y, z segment) sums
+// |a_x|^2 over x = deposit(y, S) | deposit(z, ~S) for z in the segment, each
+// lane in increasing z, then a fixed butterfly over the lanes; a second
+// kernel adds the segments in order.
+struct MargArgs {
+    uint64_t smask, zmask;
+    int32_t nq, pad;
+    uint64_t zseg;          // z values per segment
+    uint32_t nseg;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_marg_partial(const c2_t<R> *__restrict__ a, MargArgs M,
+                                                         double *__restrict__ part)
+{
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nbins = 1ull << M.nq;
+    if (wave >= nbins * M.nseg) return;
+    const uint64_t y = wave % nbins, seg = wave / nbins;
+    const uint64_t xy = deposit(y, M.smask);
+    double acc = 0.0;
+    const uint64_t z0 = seg * M.zseg;
+    for (uint64_t z = z0 + lane; z < z0 + M.zseg; z += 64) {
+        const c2_t<R> v = a[xy | deposit(z, M.zmask)];
+        const double re = (double)v.x, im = (double)v.y;
+        acc += re * re + im * im;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) part[seg * nbins + y] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_marg_final(const double *__restrict__ part, uint64_t nbins,
+                                                       uint32_t nseg, double *__restrict__ out)
+{
+    const uint64_t y = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (y >= nbins) return;
+    double s = 0.0;
+    for (uint32_t g = 0; g < nseg; ++g) s += part[(uint64_t)g * nbins + y];
+    out[y] = s;
+}
+
+// <a|b> in FP64: every block sums a fixed strided sequence per thread, then
+// a fixed tree over the block; a second kernel adds the block results in a
+// fixed tree.
+constexpr uint32_t kInnerBlocks = 2048;
+
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kBlock) void k_inner_partial(const c2_t<RA> *__restrict__ a,
+                                                          const c2_t<RB> *__restrict__ b, uint64_t len,
+                                                          double2 *__restrict__ part)
+{
+    __shared__ double sre[kBlock], sim[kBlock];
+    double re = 0.0, im = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < len; x += stride) {
+        const double ar = (double)a[x].x, ai = (double)a[x].y;
+        const double br = (double)b[x].x, bi = (double)b[x].y;
+        re += ar * br + ai * bi;
+        im += ar * bi - ai * br;
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sre[0], sim[0]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_inner_final(const double2 *__restrict__ part, uint32_t n,
+                                                        double *__restrict__ out)
+{
+    __shared__ double sre[kBlock], sim[kBlock];
+    double re = 0.0, im = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+        re += part[i].x;
+        im += part[i].y;
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sre[0];
+        out[1] = sim[0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_init(void *state, int n, hipStream_t s)
+{
+    const uint64_t len = 1ull << n;
+    k_init<R><<<blocks_for(len, kBlock * 4), kBlock, 0, s>>>((c2_t<R> *)state, len);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dense(void *state, int n, const GateDesc &g, const void *mat, hipStream_t s)
+{
+    const int k = (int)g.k;
+    if (k < 1 || k > 6 || k > n) return hipErrorInvalidValue;
+    const uint64_t ng = 1ull << (n - k);
+    const uint32_t nb = blocks_for(ng, kBlock);
+    auto *a = (c2_t<R> *)state;
+    auto *m = (const c2_t<R> *)mat;
+    switch (k) {
+    case 1: k_dense<R, 1><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    case 2: k_dense<R, 2><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    case 3: k_dense<R, 3><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    case 4: k_dense<R, 4><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    case 5: k_dense<R, 5><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    default: k_dense<R, 6><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_diag_q(void *state, int n, int k, const int *q, const void *table, hipStream_t s)
+{
+    if (k < 1 || k > 24 || k > n) return hipErrorInvalidValue;
+    DiagArgs d{};
+    d.k = k;
+    for (int t = 0; t < k; ++t) d.q[t] = q[t];
+    const uint64_t len = 1ull << n;
+    k_diag<R><<<blocks_for(len, kBlock * 2), kBlock, 0, s>>>((c2_t<R> *)state, (const c2_t<R> *)table, len, d);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_kron(void *dst, const void *lo, int nlo, const void *hi, int nhi, hipStream_t s)
+{
+    const uint64_t len = 1ull << (nlo + nhi);
+    k_kron<R><<<blocks_for(len, kBlock), kBlock, 0, s>>>((c2_t<R> *)dst, (const c2_t<R> *)lo,
+                                                         (const c2_t<R> *)hi, nlo, len);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_perm(void *dst, const void *src, int n, const int *perm, hipStream_t s)
+{
+    if (n < 1 || n > 40) return hipErrorInvalidValue;
+    PermArgs p{};
+    p.n = n;
+    for (int b = 0; b < n; ++b) p.perm[b] = perm[b];
+    const uint64_t len = 1ull << n;
+    k_perm<R><<<blocks_for(len, kBlock), kBlock, 0, s>>>((c2_t<R> *)dst, (const c2_t<R> *)src, len, p);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gather(const void *state, const uint64_t *idx, uint64_t m, double *out, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    k_gather<R><<<blocks_for(m, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, idx, m, (double2 *)out);
+    return hipGetLastError();
+}
+
+namespace {
+void marg_shape(int n, int nq, uint64_t *zseg, uint32_t *nseg)
+{
+    const uint64_t nz = 1ull << (n - nq);
+    // aim for >= 2^16 waves in flight when the bins alone give fewer
+    uint64_t seg = 1;
+    const uint64_t nbins = 1ull << nq;
+    while (nbins * seg < (1ull << 16) && nz / (seg * 2) >= 256) seg *= 2;
+    *nseg = (uint32_t)seg;
+    *zseg = nz / seg;
+}
+}  // namespace
+
+size_t marginal_scratch_bytes(int n, int nq)
+{
+    uint64_t zseg;
+    uint32_t nseg;
+    marg_shape(n, nq, &zseg, &nseg);
+    return (size_t)nseg * (1ull << nq) * sizeof(double);
+}
+
+template <typename R>
+hipError_t launch_marginal(const void *state, int n, const int *q, int nq, double *out, double *scratch,
+                           hipStream_t s)
+{
+    if (nq < 0 || nq > n || nq > 20) return hipErrorInvalidValue;
+    MargArgs M{};
+    for (int t = 0; t < nq; ++t) M.smask |= 1ull << q[t];
+    M.zmask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~M.smask;
+    M.nq = nq;
+    // y bit t <-> qubit q[t]: deposit() fills ascending positions, so the
+    // bins come out in ascending-qubit order; the executor passes q sorted and
+    // reorders on the host.
+    marg_shape(n, nq, &M.zseg, &M.nseg);
+    const uint64_t nbins = 1ull << nq;
+    const uint64_t waves = nbins * M.nseg;
+    k_marg_partial<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, M, scratch);
+    k_marg_final<<<blocks_for(nbins, kBlock), kBlock, 0, s>>>(scratch, nbins, M.nseg, out);
+    return hipGetLastError();
+}
+
+size_t inner_scratch_bytes(int n)
+{
+    (void)n;
+    return kInnerBlocks * sizeof(double2);
+}
+
+template <typename RA, typename RB>
+hipError_t launch_inner(const void *a, const void *b, int n, double *out, double *scratch, hipStream_t s)
+{
+    const uint64_t len = 1ull << n;
+    uint32_t nb = blocks_for(len, kBlock * 8);
+    if (nb > kInnerBlocks) nb = kInnerBlocks;
+    k_inner_partial<RA, RB><<<nb, kBlock, 0, s>>>((const c2_t<RA> *)a, (const c2_t<RB> *)b, len,
+                                                  (double2 *)scratch);
+    k_inner_final<<<1, kBlock, 0, s>>>((const double2 *)scratch, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s)
+{
+    const uint64_t n16 = bytes / 16;
+    uint32_t nb = blocks_for(n16, kBlock * 4);
+    if (nb > 65536) nb = 65536;
+    k_copy<<<nb, kBlock, 0, s>>>((uint4 *)dst, (const uint4 *)src, n16);
+    return hipGetLastError();
+}
+
+#define QS_INST(R)                                                                                       \
+    template hipError_t launch_init<R>(void *, int, hipStream_t);                                       \
+    template hipError_t launch_dense<R>(void *, int, const GateDesc &, const void *, hipStream_t);      \
+    template hipError_t launch_diag_q<R>(void *, int, int, const int *, const void *, hipStream_t);     \
+    template hipError_t launch_kron<R>(void *, const void *, int, const void *, int, hipStream_t);      \
+    template hipError_t launch_perm<R>(void *, const void *, int, const int *, hipStream_t);            \
+    template hipError_t launch_gather<R>(const void *, const uint64_t *, uint64_t, double *, hipStream_t); \
+    template hipError_t launch_marginal<R>(const void *, int, const int *, int, double *, double *, hipStream_t);
+QS_INST(double)
+QS_INST(float)
+template hipError_t launch_inner<double, double>(const void *, const void *, int, double *, double *, hipStream_t);
+template hipError_t launch_inner<double, float>(const void *, const void *, int, double *, double *, hipStream_t);
+template hipError_t launch_inner<float, double>(const void *, const void *, int, double *, double *, hipStream_t);
+template hipError_t launch_inner<float, float>(const void *, const void *, int, double *, double *, hipStream_t);
+
+}  // namespace qs

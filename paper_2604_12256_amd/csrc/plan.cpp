@@ -1,0 +1,665 @@
+// Host optimiser: builds the execution plan of a circuit.
+//
+// Pass order follows the swarm optimisation of Sec. 4.2 (Alg. 4) on one
+// device (no rank level):
+//   merge booster (Sec. 4.4, Alg. 6-7) -> diagonal detector (Sec. 4.5, Alg. 8)
+//   -> gate block search with limit C (cache-blocked stages, Alg. 2)
+//   -> gate block search with limit F and fusion inside every block.
+// Every pass keeps the state the circuit defines (Alg. 1) up to rounding.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <stdexcept>
+
+#include "ir.hpp"
+
+namespace qs {
+
+namespace {
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// FMA per amplitude of one operator applied to registers (cost model).
+double op_cost(bool diag, int dense_qubits) { return diag ? 4.0 : 4.0 * double(1 << dense_qubits); }
+// Floating-point operations per amplitude: a dense k-qubit operator does 2^k
+// complex multiply-adds (8 flops each), a diagonal one complex multiply (6).
+double op_flops(bool diag, int dense_qubits) { return diag ? 6.0 : 8.0 * double(1 << dense_qubits); }
+
+}  // namespace
+
+Options resolve_options(const sim_options *o, sim_dtype dtype, int n)
+{
+    Options r;
+    if (o) {
+        r.opt = o->opt;
+        r.C = o->C;
+        r.F = o->F ? o->F : 5;
+        r.D = o->D ? o->D : 10;
+        r.B = o->B ? o->B : 4;
+        r.force_fuse_k = o->force_fuse_k;
+    }
+    r.reg_bits = dtype == SIM_C128 ? 4 : 5;
+    if (r.C == 0) r.C = dtype == SIM_C128 ? 13 : 14;
+    if (r.F > 6) r.F = 6;
+    if (r.D > 20) r.D = 20;
+    if (r.D < 1) r.D = 1;
+    if (r.B < 1) r.B = 1;
+    (void)n;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Merge booster, divide component (Alg. 6): halve N (floor half first, then the
+// ceiling half) until a part is at most div_size; leaves are queued in order.
+void divider(int n, int div_size, std::vector<int> &que)
+{
+    if (n <= div_size) {
+        que.push_back(n);
+        return;
+    }
+    divider(n >> 1, div_size, que);
+    int m = (n & 1) ? n + 1 : n;
+    divider(m >> 1, div_size, que);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal detector (Alg. 8).  Readings where the listing is silent or
+// inconsistent:
+//  * a run holding a single diagonal is emitted unchanged (the listing only
+//    emits runs of two or more);
+//  * a non-diagonal gate is deferred to the unprocessed list when it touches
+//    a qubit of an earlier diagonal of the run OR a qubit of an already
+//    deferred gate, so two non-commuting gates are never reordered;
+//  * deferring marks every qubit of the deferred gate in the stop table;
+//  * a diagonal stops the run when it touches a marked qubit or when the union
+//    of the run's qubits would exceed D (the practical upper bound of
+//    Sec. 4.5); the scan then restarts at that gate.
+// The fused table is the product of the members' diagonals on the ascending
+// union of their qubits.
+std::vector<Operator> diagonal_detector(int n, int D, const std::vector<Operator> &in, uint64_t *visits)
+{
+    (void)n;
+    std::vector<Operator> res;
+    res.reserve(in.size());
+    uint64_t placed = 0;
+    size_t it = 0;
+    while (it < in.size()) {
+        const Operator &g = in[it];
+        if (!g.diag) {
+            res.push_back(g);
+            ++placed;
+            ++it;
+            continue;
+        }
+        std::vector<size_t> diag_list{it};
+        std::vector<size_t> u_list;
+        uint64_t stop = 0, dep = g.mask(), uni = g.mask();
+        size_t f = it + 1;
+        for (; f < in.size(); ++f) {
+            const Operator &h = in[f];
+            const uint64_t hm = h.mask();
+            if (!h.diag) {
+                if (hm & (dep | stop)) {
+                    stop |= hm;
+                    u_list.push_back(f);
+                } else {
+                    res.push_back(h);
+                    ++placed;
+                }
+            } else {
+                if ((hm & stop) || popc(uni | hm) > D) break;
+                dep |= hm;
+                uni |= hm;
+                diag_list.push_back(f);
+            }
+        }
+        if (diag_list.size() == 1) {
+            res.push_back(g);
+        } else {
+            std::vector<int> qs;
+            for (int q = 0; q < 64; ++q)
+                if ((uni >> q) & 1) qs.push_back(q);
+            Operator acc;
+            acc.q = qs;
+            acc.diag = true;
+            acc.m.assign(1ull << qs.size(), cplx(1.0, 0.0));
+            for (size_t idx : diag_list) apply_left(acc, in[idx]);
+            res.push_back(std::move(acc));
+        }
+        placed += diag_list.size();
+        for (size_t idx : u_list) res.push_back(in[idx]);
+        placed += u_list.size();
+        it = f;
+    }
+    if (visits) *visits = placed;
+    return res;
+}
+
+namespace {
+
+// Qubits a gate needs in registers (and hence local) inside a stage: those on
+// which it is not block diagonal.  A dense gate selecting its block by more
+// than two qubits, or a 3+ qubit dense gate selecting by any, keeps all its
+// qubits (the stage kernel takes at most two block-selecting bits, and
+// lane-bit selection only for 1- and 2-bit operators).
+uint64_t tile_need(const Operator &g)
+{
+    uint64_t need = need_mask(g);
+    if (!g.diag && (popc(g.mask() & ~need) > 2 || (popc(need) > 2 && (g.mask() & ~need)))) need = g.mask();
+    return need;
+}
+
+// ---------------------------------------------------------------------------
+// Plan assembly helpers.
+
+struct Builder {
+    Plan &plan;
+    const Options &o;
+
+    double amp_bytes() const { return plan.dtype == SIM_C128 ? 16.0 : 8.0; }
+
+    void add_full_pass_op(int buffer, int nb, const Operator &g)
+    {
+        PlanOp op;
+        op.kind = g.diag ? SIM_OP_DIAG : SIM_OP_DENSE;
+        op.buffer = buffer;
+        op.buffer_qubits = nb;
+        op.op = g;
+        const double amps = std::ldexp(1.0, nb);
+        op.flops = op_flops(g.diag, g.k()) * amps;
+        op.bytes = 2.0 * amps * amp_bytes();
+        plan.ops.push_back(std::move(op));
+    }
+
+    // Fusion inside one phase: greedy merging of consecutive gates into one
+    // operator while the fused operator costs no more FMA per amplitude than
+    // its members applied one by one (cost-based fusion with the register
+    // tile as the size limit).  A fused dense operator acts on 1, 2 or all r
+    // register bits (the kernel's code paths) and may select its block by at
+    // most two non-register qubits; selection by a lane bit is only allowed
+    // for 1- and 2-bit operators (their matrices are then loaded per lane).
+    void fuse_phase(Phase &ph, const std::vector<const Operator *> &gates, const std::vector<int> &reg_phys,
+                    uint64_t lane_phys, double *flops_per_amp)
+    {
+        const int r = (int)reg_phys.size();
+        auto regbit = [&](int phys) {
+            for (int b = 0; b < r; ++b)
+                if (reg_phys[b] == phys) return b;
+            return -1;
+        };
+        const int kTmax = 2;
+        const uint32_t full = (1u << r) - 1;
+        auto kernel_mask = [&](uint32_t S) { return popc(S) >= 3 ? full : S; };
+        auto dense_cost = [&](uint32_t S) { return op_cost(false, popc(kernel_mask(S))); };
+        auto lane_sel = [&](const std::vector<int> &T) {
+            for (int t : T)
+                if ((lane_phys >> t) & 1) return true;
+            return false;
+        };
+        struct Block {
+            bool open = false;
+            uint32_t S = 0;
+            std::vector<int> T;
+            Operator acc;
+            double indiv = 0;
+        } F;
+        auto qlist = [&](uint32_t S, const std::vector<int> &T) {
+            std::vector<int> l;
+            for (int b = 0; b < r; ++b)
+                if ((S >> b) & 1) l.push_back(reg_phys[b]);
+            for (int t : T) l.push_back(t);
+            return l;
+        };
+        auto push_diag = [&](const std::vector<int> &q, const std::vector<cplx> &table) {
+            KOp k;
+            k.type = KOp::DIAG;
+            k.dq = q;
+            k.table = table;
+            *flops_per_amp += op_flops(true, 0);
+            ph.ops.push_back(std::move(k));
+        };
+        auto emit = [&](Block &B) {
+            if (!B.open) return;
+            if (B.acc.diag) {
+                push_diag(B.acc.q, B.acc.m);
+            } else {
+                KOp k;
+                k.type = KOp::DENSE;
+                const uint32_t km = kernel_mask(B.S);
+                if (km != B.S) B.acc = embed(B.acc, qlist(km, B.T));
+                k.reg_mask = km;
+                k.sel = B.T;
+                const int ks = popc(km);
+                std::vector<int> fixed_pos;
+                for (size_t u = 0; u < B.T.size(); ++u) fixed_pos.push_back(ks + (int)u);
+                for (uint64_t sel = 0; sel < (1ull << B.T.size()); ++sel) {
+                    std::vector<cplx> blk = sub_block(B.acc, fixed_pos, sel);
+                    k.table.insert(k.table.end(), blk.begin(), blk.end());
+                }
+                *flops_per_amp += op_flops(false, ks);
+                ph.ops.push_back(std::move(k));
+            }
+            B = Block();
+        };
+        for (const Operator *gp : gates) {
+            const Operator &g = *gp;
+            uint32_t gS = 0;
+            std::vector<int> gT;
+            for (int x : g.q) {
+                int b = regbit(x);
+                if (b >= 0) gS |= 1u << b;
+                else gT.push_back(x);
+            }
+            if (g.diag && g.k() > 3) {  // a wide diagonal (diagonal detector output): its own table
+                emit(F);
+                push_diag(g.q, g.m);
+                continue;
+            }
+            const double gcost = g.diag ? op_cost(true, 0) : dense_cost(gS);
+            if (F.open) {
+                const uint32_t S2 = F.S | gS;
+                std::vector<int> T2 = F.T;
+                for (int x : gT)
+                    if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
+                const bool diag2 = F.acc.diag && g.diag;
+                const double fused = diag2 ? op_cost(true, 0) : dense_cost(S2);
+                const bool sel_ok = (int)T2.size() <= kTmax && (diag2 || popc(kernel_mask(S2)) <= 2 || !lane_sel(T2));
+                if (sel_ok && fused <= F.indiv + gcost + 1e-9) {
+                    std::vector<int> l2 = qlist(S2, T2);
+                    if (l2 != F.acc.q) F.acc = embed(F.acc, l2);
+                    apply_left(F.acc, g);
+                    F.S = S2;
+                    F.T = T2;
+                    F.indiv += gcost;
+                    continue;
+                }
+                emit(F);
+            }
+            const bool alone_ok = (int)gT.size() <= kTmax && (g.diag || popc(kernel_mask(gS)) <= 2 || !lane_sel(gT));
+            if (!alone_ok) {
+                if (g.diag) {
+                    push_diag(g.q, g.m);
+                    continue;
+                }
+                throw std::runtime_error("fuse_phase: dense gate needs more register bits");
+            }
+            F.open = true;
+            F.S = gS;
+            F.T = gT;
+            F.acc = embed(g, qlist(gS, gT));
+            F.indiv = gcost;
+        }
+        emit(F);
+    }
+
+    // Register phases of one stage: gate block search with limit r on the
+    // qubits each gate needs in registers, over the stage's gate list (the
+    // same search as the stage partition, one level down the memory
+    // hierarchy).  At most kMaxPhases phases; the gates beyond are returned.
+    static constexpr int kMaxPhases = 96;
+
+    std::vector<int> make_phases(PlanOp &st, const std::vector<Operator> &all, const std::vector<int> &idx,
+                                 double *flops)
+    {
+        const int r = o.reg_bits, C = (int)st.local.size();
+        int local_of[64];
+        for (int q = 0; q < 64; ++q) local_of[q] = -1;
+        for (int i = 0; i < C; ++i) local_of[st.local[i]] = i;
+        std::vector<int> rem = idx;
+        std::vector<int> prev;
+        for (int b = 0; b < r; ++b) prev.push_back(C - r + b);  // load mapping
+        double fpa = 0;
+        while (!rem.empty() && (int)st.phases.size() < kMaxPhases) {
+            uint64_t R = 0, blocked = 0;  // R over local bit indices
+            std::vector<int> take, left;
+            for (int gi : rem) {
+                const Operator &g = all[gi];
+                const uint64_t qs = g.mask();
+                if (qs & blocked) {
+                    blocked |= qs;
+                    left.push_back(gi);
+                    continue;
+                }
+                uint64_t nd = 0;
+                const uint64_t need = tile_need(g);
+                for (int q = 0; q < 64; ++q)
+                    if ((need >> q) & 1) {
+                        if (local_of[q] < 0) throw std::runtime_error("make_phases: qubit not local");
+                        nd |= 1ull << local_of[q];
+                    }
+                if (popc(R | nd) <= r) {
+                    R |= nd;
+                    take.push_back(gi);
+                } else {
+                    blocked |= qs;
+                    left.push_back(gi);
+                }
+            }
+            if (take.empty()) throw std::runtime_error("make_phases: no progress");
+            for (int b : prev)  // keep previous register bits where free
+                if (popc(R) < r) R |= 1ull << b;
+            for (int i = C - 1; i >= 0 && popc(R) < r; --i) R |= 1ull << i;
+            Phase ph;
+            for (int i = 0; i < C; ++i)
+                if ((R >> i) & 1) ph.reg.push_back(i);
+            std::vector<int> reg_phys;
+            for (int i : ph.reg) reg_phys.push_back(st.local[i]);
+            uint64_t lane_phys = 0;
+            for (int i = 0, cnt = 0; i < C && cnt < 6; ++i)
+                if (!((R >> i) & 1)) {
+                    lane_phys |= 1ull << st.local[i];
+                    ++cnt;
+                }
+            std::vector<const Operator *> tg;
+            for (int gi : take) {
+                tg.push_back(&all[gi]);
+                st.gates.push_back(all[gi]);
+            }
+            fuse_phase(ph, tg, reg_phys, lane_phys, &fpa);
+            st.phases.push_back(std::move(ph));
+            prev = st.phases.back().reg;
+            rem.swap(left);
+        }
+        *flops += fpa;
+        return rem;
+    }
+
+    // Gate block search with limit C over the gates of one buffer (Alg. 4,
+    // GBSA(N, C)): greedy DAG frontier; a gate joins the open stage when none
+    // of its qubits is blocked and its locally-needed qubits fit; otherwise all
+    // its qubits become blocked.  Diagonal gates and block-selecting (control)
+    // qubits need not be local: inside a chunk the other bits are constants.
+    void stages(int buffer, int nb, const std::vector<Operator> &gates)
+    {
+        const int C = std::min<int>((int)o.C, nb), r = o.reg_bits;
+        const int low = std::min(o.fixed_low, C);
+        std::vector<int> rem(gates.size());
+        for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
+        const double nb_amps = std::ldexp(1.0, nb);
+        while (!rem.empty()) {
+            const Operator &first = gates[rem.front()];
+            if (popc(tile_need(first)) > r) {  // beyond the register tile: one full pass
+                add_full_pass_op(buffer, nb, first);
+                account_full_pass(buffer, nb, first);
+                rem.erase(rem.begin());
+                continue;
+            }
+            uint64_t L = (1ull << low) - 1;
+            uint64_t blocked = 0;
+            std::vector<int> take, left;
+            for (int gi : rem) {
+                const Operator &g = gates[gi];
+                const uint64_t qs = g.mask();
+                const uint64_t nd = tile_need(g);
+                if ((qs & blocked) || popc(nd) > r) {
+                    blocked |= qs;
+                    left.push_back(gi);
+                    continue;
+                }
+                if (popc(L | nd) <= C) {
+                    L |= nd;
+                    take.push_back(gi);
+                } else {
+                    blocked |= qs;
+                    left.push_back(gi);
+                }
+            }
+            for (int q = 0; q < nb && popc(L) < C; ++q) L |= 1ull << q;
+            PlanOp st;
+            st.kind = SIM_OP_STAGE;
+            st.buffer = buffer;
+            st.buffer_qubits = nb;
+            for (int q = 0; q < nb; ++q)
+                if ((L >> q) & 1) st.local.push_back(q);
+            double fpa = 0;
+            std::vector<int> over = make_phases(st, gates, take, &fpa);
+            st.flops = fpa * nb_amps;
+            st.bytes = 2.0 * nb_amps * amp_bytes();
+            plan.stats.flops += st.flops;
+            if (buffer == 0) {
+                plan.stats.full_passes += 1;
+                plan.stats.bytes += 2.0 * nb_amps * amp_bytes();
+                plan.stats.n_stages += 1;
+            } else {
+                plan.stats.n_subruns += 1;
+            }
+            plan.ops.push_back(std::move(st));
+            if (!over.empty()) {  // phase cap hit: the rest goes back, in circuit order
+                left.insert(left.end(), over.begin(), over.end());
+                std::sort(left.begin(), left.end());
+            }
+            rem.swap(left);
+        }
+    }
+
+    void account_full_pass(int buffer, int nb, const Operator &g)
+    {
+        const double amps = std::ldexp(1.0, nb);
+        if (buffer != 0) {
+            plan.stats.n_subruns += 1;
+            return;
+        }
+        plan.stats.full_passes += 1;
+        plan.stats.bytes += 2.0 * amps * amp_bytes();
+        plan.stats.flops += op_flops(g.diag, g.k()) * amps;
+        if (g.diag) plan.stats.n_diag += 1;
+        else plan.stats.n_dense += 1;
+    }
+
+    // Gate block search with limit F and fusion (Alg. 4, GBSA(N, F, GB, 1)):
+    // blocks of at most F qubits; a block is fused into one operator when that
+    // costs no more than its members (or always, with force_fuse_k).
+    void fused_passes(int buffer, int nb, const std::vector<Operator> &gates)
+    {
+        const int F = o.force_fuse_k ? (int)o.force_fuse_k : (int)o.F;
+        std::vector<const Operator *> rem;
+        for (const Operator &g : gates) rem.push_back(&g);
+        while (!rem.empty()) {
+            uint64_t U = 0, blocked = 0;
+            std::vector<const Operator *> take, left;
+            for (const Operator *g : rem) {
+                const uint64_t qs = g->mask();
+                if (qs & blocked) {
+                    blocked |= qs;
+                    left.push_back(g);
+                    continue;
+                }
+                if (popc(U | qs) <= F || take.empty()) {
+                    U |= qs;
+                    take.push_back(g);
+                } else {
+                    blocked |= qs;
+                    left.push_back(g);
+                }
+            }
+            // full-pass cost of the members one by one vs fused: the state is
+            // read and written once per op, so fusing saves passes; dense
+            // arithmetic grows as 2^k (cost model: passes dominate up to F).
+            bool all_diag = true;
+            for (const Operator *g : take) all_diag &= g->diag;
+            std::vector<int> ql;
+            for (int q = 0; q < 64; ++q)
+                if ((U >> q) & 1) ql.push_back(q);
+            if (take.size() == 1) {
+                add_full_pass_op(buffer, nb, *take[0]);
+                account_full_pass(buffer, nb, *take[0]);
+            } else {
+                Operator acc;
+                acc.q = ql;
+                acc.diag = all_diag;
+                if (all_diag) acc.m.assign(1ull << ql.size(), cplx(1.0, 0.0));
+                else {
+                    const uint64_t d = 1ull << ql.size();
+                    acc.m.assign(d * d, cplx(0.0, 0.0));
+                    for (uint64_t i = 0; i < d; ++i) acc.m[i * d + i] = 1.0;
+                }
+                for (const Operator *g : take) apply_left(acc, *g);
+                add_full_pass_op(buffer, nb, acc);
+                account_full_pass(buffer, nb, acc);
+            }
+            rem.swap(left);
+        }
+    }
+
+    // Executes the gates of one buffer with the enabled passes.
+    void lower(int buffer, int nb, std::vector<Operator> gates)
+    {
+        if (o.opt & SIM_OPT_DIAG) {
+            uint64_t v = 0;
+            gates = diagonal_detector(nb, (int)o.D, gates, &v);
+            plan.stats.dd_visits += v;
+        }
+        if (gates.empty()) return;
+        const bool small = buffer != 0 && nb <= (plan.dtype == SIM_C128 ? 13 : 14);
+        if ((o.opt & SIM_OPT_STAGES) && small) {
+            // the whole sub-state is one chunk: one launch runs its gate list
+            PlanOp st;
+            st.kind = SIM_OP_STAGE;
+            st.buffer = buffer;
+            st.buffer_qubits = nb;
+            for (int q = 0; q < nb; ++q) st.local.push_back(q);
+            st.gates = std::move(gates);
+            plan.stats.n_subruns += 1;
+            plan.ops.push_back(std::move(st));
+            return;
+        }
+        if ((o.opt & SIM_OPT_STAGES) && nb >= o.fixed_low + o.reg_bits) {
+            stages(buffer, nb, gates);
+        } else if (o.opt & SIM_OPT_FUSE) {
+            fused_passes(buffer, nb, gates);
+        } else {
+            for (const Operator &g : gates) {
+                add_full_pass_op(buffer, nb, g);
+                account_full_pass(buffer, nb, g);
+            }
+        }
+    }
+
+    void init_op(int buffer, int nb)
+    {
+        PlanOp op;
+        op.kind = SIM_OP_INIT;
+        op.buffer = buffer;
+        op.buffer_qubits = nb;
+        op.bytes = std::ldexp(1.0, nb) * amp_bytes();
+        plan.ops.push_back(std::move(op));
+        if (buffer == 0) {
+            plan.stats.write_passes += 1;
+            plan.stats.bytes += std::ldexp(1.0, nb) * amp_bytes();
+        }
+    }
+
+    // Merge booster (Alg. 7) with these readings: groups are contiguous qubit
+    // ranges starting at qubit 0 (the listing counts from 1); the gate block
+    // of a group takes every gate whose qubits lie inside the group and that
+    // no earlier, untaken gate shares a qubit with (so the block is a prefix
+    // of the remaining circuit restricted to the group, and the group stays
+    // unentangled from the rest while it runs); an unpaired trailing group is
+    // carried to the next round unchanged (the listing would drop it); the
+    // division size is ceil(N / B) as in the listing.
+    std::vector<Operator> booster(const std::vector<Operator> &gates)
+    {
+        const int n = plan.n;
+        std::vector<int> que;
+        divider(n, (n + (int)o.B - 1) / (int)o.B, que);
+        if (que.size() <= 1) {
+            init_op(0, n);
+            return gates;
+        }
+        struct Group { int lo, len, buffer; };
+        std::vector<Group> groups;
+        int acc = 0;
+        for (int len : que) {
+            Group g{acc, len, (int)plan.buffer_qubits.size()};
+            plan.buffer_qubits.push_back(len);
+            groups.push_back(g);
+            init_op(g.buffer, len);
+            acc += len;
+        }
+        plan.stats.booster_groups += groups.size();
+        std::vector<Operator> rest = gates;
+        std::vector<char> taken(rest.size(), 0);
+        while (true) {
+            // generation step for every group of this round
+            for (const Group &G : groups) {
+                const uint64_t gm = (G.len >= 64 ? ~0ull : ((1ull << G.len) - 1)) << G.lo;
+                uint64_t blocked = 0;
+                std::vector<Operator> block;
+                for (size_t i = 0; i < rest.size(); ++i) {
+                    if (taken[i]) continue;
+                    const uint64_t qs = rest[i].mask();
+                    if ((qs & ~gm) || (qs & blocked)) {
+                        blocked |= qs;
+                        continue;
+                    }
+                    taken[i] = 1;
+                    Operator local = rest[i];
+                    for (int &q : local.q) q -= G.lo;
+                    block.push_back(std::move(local));
+                }
+                plan.stats.booster_gates += block.size();
+                lower(G.buffer, G.len, std::move(block));
+            }
+            if (groups.size() == 1) break;
+            // merge step: pairs (0,1), (2,3), ...; an odd last group carries over
+            std::vector<Group> next;
+            for (size_t i = 0; i + 1 < groups.size(); i += 2) {
+                const Group &A = groups[i], &Bg = groups[i + 1];
+                Group M{A.lo, A.len + Bg.len, 0};
+                if (M.len == plan.n) M.buffer = 0;
+                else {
+                    M.buffer = (int)plan.buffer_qubits.size();
+                    plan.buffer_qubits.push_back(M.len);
+                }
+                PlanOp k;
+                k.kind = SIM_OP_KRON;
+                k.buffer = M.buffer;
+                k.buffer_qubits = M.len;
+                k.src_lo = A.buffer;
+                k.src_hi = Bg.buffer;
+                k.bytes = std::ldexp(1.0, M.len) * amp_bytes();
+                k.flops = 6.0 * std::ldexp(1.0, M.len);
+                plan.ops.push_back(std::move(k));
+                if (M.buffer == 0) {
+                    plan.stats.write_passes += 1;
+                    plan.stats.bytes += std::ldexp(1.0, M.len) * amp_bytes();
+                    plan.stats.n_kron += 1;
+                }
+                next.push_back(M);
+            }
+            if (groups.size() & 1) next.push_back(groups.back());
+            groups.swap(next);
+            if (groups.size() == 1 && groups[0].buffer == 0) break;
+        }
+        std::vector<Operator> left;
+        for (size_t i = 0; i < rest.size(); ++i)
+            if (!taken[i]) left.push_back(rest[i]);
+        return left;
+    }
+};
+
+}  // namespace
+
+void build_plan(Plan &plan, const std::vector<Operator> &gates)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    plan.ops.clear();
+    plan.stats = PlanStats();
+    plan.buffer_qubits.assign(1, plan.n);
+    plan.layout.resize(plan.n);
+    for (int q = 0; q < plan.n; ++q) plan.layout[q] = q;
+    Builder b{plan, plan.opt};
+    std::vector<Operator> rest;
+    if (plan.opt.opt & SIM_OPT_BOOST) {
+        rest = b.booster(gates);
+    } else {
+        b.init_op(0, plan.n);
+        rest = gates;
+    }
+    b.lower(0, plan.n, std::move(rest));
+    plan.stats.n_ops = plan.ops.size();
+    auto t1 = std::chrono::steady_clock::now();
+    plan.stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+}  // namespace qs

@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance: max |delta a| <= 1e-12 for complex128 (the accuracy target of the
+simulator); complex64 states are compared by infidelity <= 1e-6 and
+max |delta a| <= 2e-5 * max |a| (single precision rounding over a few
+thousand gates).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_12256_amd import qsim
+from paper_2604_12256_amd import workloads as W
+from paper_2604_12256_amd.workloads import Gate
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_state(n, gates, dtype="c128", **kw):
+    sim = qsim.Simulator(n, dtype=dtype, **kw)
+    sim.load(gates)
+    sim.run()
+    out = sim.amplitudes()
+    st = sim.stats()
+    sim.close()
+    return out, st
+
+
+def check128(got, want, what=""):
+    err = np.max(np.abs(got - want))
+    assert err <= TOL128, f"{what}: max|delta| = {err:.3e}"
+    return err
+
+
+def check64(got, want, oracle_mod, what=""):
+    inf = oracle_mod.infidelity(want, got.astype(np.complex128))
+    err = np.max(np.abs(got - want))
+    assert inf <= 1e-6, f"{what}: infidelity {inf:.3e}"
+    assert err <= 2e-5 * np.max(np.abs(want)) + 1e-7, f"{what}: max|delta| {err:.3e}"
+
+
+def test_layered12_plain_full_state(oracle_mod):
+    """12-qubit layered circuit on the plain gate-by-gate path, full state."""
+    n, gates = W.config_circuit("layered12")
+    say("layered12 plain")
+    got, st = gpu_state(n, gates, opt=0)
+    assert st["full_passes"] == 540
+    check128(got, oracle_mod.run(n, gates), "layered12 plain")
+
+
+@pytest.mark.parametrize("opt", [0, 1, 2, 3, 4, 6, 7, 8, 12, 14, 15])
+def test_random_circuits_every_pass(oracle_mod, opt):
+    for n, seed, C in ((11, 1, 10), (14, 2, 12), (16, 3, 13), (15, 4, 11)):
+        gates = W.random_mixed(n, 120, seed=seed + 7 * opt, max_k=5)
+        say(f"random n={n} opt={opt} C={C}")
+        got, _ = gpu_state(n, gates, opt=opt, C=C)
+        check128(got, oracle_mod.run(n, gates), f"n={n} opt={opt}")
+
+
+@pytest.mark.parametrize("C", [10, 11, 12, 13])
+def test_stage_kernel_chunk_sizes(oracle_mod, C):
+    """Targets on register, lane, wave and global bits for every chunk size."""
+    n = 17
+    gates = W.layered(n, 6, seed=C)
+    say(f"stages n={n} C={C}")
+    got, st = gpu_state(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE, C=C)
+    assert st["n_stages"] >= 2
+    check128(got, oracle_mod.run(n, gates), f"C={C}")
+
+
+def test_layered_and_diag_heavy_all_opts(oracle_mod):
+    for n, gates in ((18, W.layered(18, 10, 5)), (18, W.diag_heavy(18, 300, 6)), (20, W.layered(20, 5, 7))):
+        want = oracle_mod.run(n, gates)
+        for opt in (qsim.OPT_ALL, qsim.OPT_STAGES | qsim.OPT_FUSE, qsim.OPT_FUSE | qsim.OPT_DIAG):
+            say(f"n={n} opt={opt}")
+            got, _ = gpu_state(n, gates, opt=opt)
+            check128(got, want, f"n={n} opt={opt}")
+
+
+def test_complex64_paths(oracle_mod):
+    for n, gates in ((14, W.layered(14, 10, 2)), (16, W.random_mixed(16, 150, 5, max_k=5))):
+        want = oracle_mod.run(n, gates)
+        for opt in (0, qsim.OPT_FUSE, qsim.OPT_ALL, qsim.OPT_STAGES | qsim.OPT_FUSE):
+            say(f"c64 n={n} opt={opt}")
+            got, _ = gpu_state(n, gates, dtype="c64", opt=opt, C=12 if opt & 4 else 0)
+            check64(got, want, oracle_mod, f"c64 n={n} opt={opt}")
+
+
+def test_forced_five_qubit_fusion(oracle_mod):
+    n, gates = 16, W.layered(16, 6, 11)
+    want = oracle_mod.run(n, gates)
+    for dtype in ("c128", "c64"):
+        say(f"fuse5 {dtype}")
+        got, st = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_FUSE, force_fuse_k=5)
+        if dtype == "c128":
+            check128(got, want, "fuse5")
+        else:
+            check64(got, want, oracle_mod, "fuse5 c64")
+
+
+def test_small_and_degenerate(oracle_mod):
+    for n in (1, 2, 3, 5, 9, 10):
+        gates = W.random_mixed(n, 40, seed=n, max_k=min(3, n))
+        for opt in (0, qsim.OPT_ALL):
+            got, _ = gpu_state(n, gates, opt=opt)
+            check128(got, oracle_mod.run(n, gates), f"n={n}")
+    # empty circuit: |0...0>
+    got, _ = gpu_state(12, [], opt=qsim.OPT_ALL)
+    want = np.zeros(1 << 12, dtype=np.complex128)
+    want[0] = 1
+    assert np.array_equal(got, want)
+
+
+def test_outputs_probabilities_norm_inner(oracle_mod):
+    n = 16
+    gates = W.layered(n, 8, 3)
+    want = oracle_mod.run(n, gates)
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    idx = W.sample_indices(n, 1000, 1)
+    check128(sim.amplitudes(idx), want[idx.astype(np.int64)], "gather")
+    for qs in ([], [0], [15, 3], [2, 9, 4, 0], list(range(12)), list(range(4, 16))):
+        got = sim.probabilities(qs)
+        ref = oracle_mod.marginal(want, qs) if qs else np.array([oracle_mod.norm(want)])
+        assert np.max(np.abs(got - ref)) < 1e-13, qs
+    other = qsim.Simulator(n, dtype="c64", opt=qsim.OPT_ALL)
+    other.load(gates)
+    other.run()
+    ip = sim.inner(other)
+    ref = oracle_mod.inner(want, other.amplitudes())
+    assert abs(ip - ref) < 1e-12
+    assert abs(abs(ip) - 1) < 1e-5
+    # determinism: a second run is bitwise identical
+    a1 = sim.amplitudes()
+    p1 = sim.probabilities([1, 2, 3])
+    sim.run()
+    assert np.array_equal(a1, sim.amplitudes())
+    assert np.array_equal(p1, sim.probabilities([1, 2, 3]))
+    sim.close()
+    other.close()
+
+
+def test_errors_reported():
+    sim = qsim.Simulator(8)
+    with pytest.raises(qsim.QsimError) as e:
+        sim.amplitudes()
+    assert e.value.status == qsim.E_STATE
+    with pytest.raises(qsim.QsimError) as e:
+        sim.load([Gate("H", (8,))])
+    assert e.value.status == qsim.E_INVAL
+    sim.load([Gate("H", (0,))])
+    sim.run()
+    with pytest.raises(qsim.QsimError):
+        sim.amplitudes(np.array([256], dtype=np.uint64))
+    with pytest.raises(qsim.QsimError):
+        sim.probabilities([0, 0])
+    # a failed load keeps the previous circuit
+    with pytest.raises(qsim.QsimError):
+        sim.load([Gate("CZ", (1, 1))])
+    sim.run()
+    assert abs(sim.amplitudes()[1] - 1 / math.sqrt(2)) < 1e-15
+    sim.close()
+
+
+# ---------------------------------------------------------------- full sizes
+def golden(name):
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from tests.golden.make_golden import read
+    path = os.path.join(HERE, "golden", f"{name}.txt")
+    if not os.path.exists(path):
+        pytest.skip(f"golden file {name}.txt not generated")
+    return read(name)
+
+
+@pytest.mark.parametrize("name", ["layered28", "layered30", "diag30"])
+def test_full_size_against_golden(name):
+    """Full-size workloads in the benchmark's configuration (all passes on),
+    on the oracle's stored sample amplitudes, marginals and norm."""
+    g = golden(name)
+    n, gates = W.config_circuit(name)
+    say(f"full size {name}")
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    got = sim.amplitudes(g["idx"])
+    check128(got, g["amp"], name)
+    assert abs(sim.norm() - g["norm"]) < 1e-12
+    for qs, ref in g["marginals"].items():
+        assert np.max(np.abs(sim.probabilities(list(qs)) - ref)) < 1e-12
+    sim.close()
+
+
+def test_diag24_full_state_and_samples(oracle_mod):
+    n, gates = W.config_circuit("diag24")
+    want = oracle_mod.run(n, gates)
+    say("diag24")
+    got, _ = gpu_state(n, gates, opt=qsim.OPT_ALL)
+    check128(got, want, "diag24")
+    idx = W.sample_indices(n, 1 << 20, 3).astype(np.int64)
+    check128(got[idx], want[idx], "diag24 samples")
+    assert abs(oracle_mod.norm(got) - 1) < 1e-12
+
+
+def test_product_state_closed_form_30q():
+    """Booster + tensor product at 30 qubits: single-qubit gates only."""
+    from oracle import closed_forms as CF
+    n = 30
+    gates = W.product_circuit(n, 4, seed=8)
+    idx = W.sample_indices(n, 1 << 20, 9)
+    say("product 30q")
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    check128(sim.amplitudes(idx), CF.product_state_amplitudes(n, gates, idx), "product30")
+    assert abs(sim.norm() - 1) < 1e-12
+    sim.close()
+
+
+def test_diagonal_closed_form_30q():
+    """Diagonal detector + phase tables at 30 qubits: H on all, then diagonals."""
+    from oracle import closed_forms as CF
+    n = 30
+    gates = W.hadamard_diagonal_circuit(n, 400, seed=10)
+    idx = W.sample_indices(n, 1 << 20, 11)
+    say("hadamard-diagonal 30q")
+    for opt in (qsim.OPT_ALL, qsim.OPT_DIAG | qsim.OPT_FUSE):
+        sim = qsim.Simulator(n, opt=opt)
+        sim.load(gates)
+        sim.run()
+        check128(sim.amplitudes(idx), CF.hadamard_diagonal_amplitudes(n, gates, idx), "hdiag30")
+        sim.close()
+
+
+def test_complex64_32q_against_complex128():
+    """Precision form: 32-qubit layered circuit in complex64 (FP32 MFMA
+    fused gates) against the complex128 path on the same GPU."""
+    n, gates = W.config_circuit("layered32")
+    say("layered32 c64 vs c128")
+    a = qsim.Simulator(n, dtype="c128", opt=qsim.OPT_ALL)
+    a.load(gates)
+    a.run()
+    b = qsim.Simulator(n, dtype="c64", opt=qsim.OPT_ALL)
+    b.load(gates)
+    b.run()
+    ip = a.inner(b)
+    inf = 1 - abs(ip) ** 2 / (a.norm() * b.norm())
+    say(f"layered32 infidelity {inf:.3e}")
+    assert inf <= 1e-6
+    assert abs(a.norm() - 1) < 1e-11
+    a.close()
+    b.close()

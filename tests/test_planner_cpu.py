@@ -1,0 +1,258 @@
+"""Host optimiser checks on the CPU (no GPU): every plan the library builds
+must reproduce the oracle's state when its ops are interpreted, and the
+booster / diagonal detector must behave as Sec. 4.4 and 4.5 describe."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2604_12256_amd import qsim
+from paper_2604_12256_amd import workloads as W
+from paper_2604_12256_amd.workloads import Gate
+
+from .planinterp import access_count, run_plan
+
+ALL_OPTS = list(range(16))
+
+
+def plan_state(n, gates, **kw):
+    p = qsim.Plan(n, gates, **kw)
+    ops = p.ops()
+    return ops, run_plan(ops, n, p.layout()), run_plan(ops, n, p.layout(), use_kernel_ops=False)
+
+
+@pytest.mark.parametrize("opt", ALL_OPTS)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_every_pass_combination_matches_oracle(oracle_mod, opt, dtype):
+    for n, seed in ((7, 1), (11, 2), (12, 3)):
+        gates = W.random_mixed(n, 150, seed=seed + 10 * opt, max_k=4)
+        want = oracle_mod.run(n, gates)
+        C = 10 if dtype == "c128" else 11
+        ops, got_k, got_g = plan_state(n, gates, dtype=dtype, opt=opt, C=C)
+        assert np.max(np.abs(got_g - want)) < 1e-12, (n, opt)
+        assert np.max(np.abs(got_k - want)) < 1e-12, (n, opt)
+
+
+@pytest.mark.parametrize("opt", [qsim.OPT_ALL, qsim.OPT_STAGES, qsim.OPT_STAGES | qsim.OPT_FUSE,
+                                 qsim.OPT_FUSE, qsim.OPT_BOOST | qsim.OPT_STAGES])
+def test_layered_and_diag_heavy(oracle_mod, opt):
+    for n, gates in ((12, W.layered(12, 8, 3)), (12, W.diag_heavy(12, 200, 5)), (13, W.layered(13, 4, 4))):
+        want = oracle_mod.run(n, gates)
+        for dtype, C in (("c128", 10), ("c128", 12), ("c64", 11), ("c64", 13)):
+            ops, got_k, got_g = plan_state(n, gates, dtype=dtype, opt=opt, C=C)
+            assert np.max(np.abs(got_k - want)) < 1e-12, (n, dtype, C)
+
+
+def test_wide_gates_and_controls(oracle_mod):
+    """5- and 6-qubit dense gates (beyond the register tile) and gates that
+    are block diagonal in some qubits (controls) on global qubits."""
+    n = 12
+    rng = np.random.default_rng(3)
+    gates = []
+    for i in range(40):
+        k = int(rng.integers(1, 7))
+        qs = tuple(int(x) for x in rng.choice(n, size=k, replace=False))
+        gates.append(Gate("U", qs, 0.0, W.haar_unitary(rng, 1 << k)))
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        gates.append(Gate("CNOT", (a, b)))
+    want = oracle_mod.run(n, gates)
+    for opt in (qsim.OPT_ALL, qsim.OPT_STAGES, qsim.OPT_FUSE):
+        ops, got_k, got_g = plan_state(n, gates, opt=opt, C=10)
+        assert np.max(np.abs(got_k - want)) < 1e-12
+
+
+def test_stage_invariants():
+    n, gates = 16, W.layered(16, 6, 9)
+    p = qsim.Plan(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE, C=12)
+    for op in p.ops():
+        if op["kind"] != "STAGE":
+            continue
+        local = set(op["local"])
+        assert len(local) == 12 and set(range(6)) <= local
+        for g in op["gates"]:
+            m = g["payload"]
+            if g["diagonal"]:
+                continue
+            # every qubit the operator is not block diagonal in must be local
+            k = len(g["qubits"])
+            for t, q in enumerate(g["qubits"]):
+                r = np.arange(1 << k)
+                off = ((r[:, None] ^ r[None, :]) >> t) & 1
+                if np.any(np.abs(m[off == 1]) > 0):
+                    assert q in local
+
+
+# ---------------------------------------------------------------- diagonal detector (Sec. 4.5)
+def figure4_circuit():
+    """Reconstruction of the diagonal-detector example (the figure itself is
+    not available): RZZ2, H3, RY4, RZZ5, CP6, RX7, RZZ8, CP9, a non-diagonal
+    gate 10 on a qubit of the run, RZZ11 on that qubit."""
+    return [
+        Gate("H", (0,)), Gate("H", (1,)), Gate("H", (2,)), Gate("H", (3,)), Gate("H", (4,)),  # prefix
+        Gate("RZZ", (0, 1), 0.3),      # 2
+        Gate("H", (2,)),               # 3
+        Gate("RY", (3,), 0.4),         # 4
+        Gate("RZZ", (1, 2), 0.5),      # 5
+        Gate("CPHASE", (2, 3), 0.6),   # 6
+        Gate("RX", (4,), 0.7),         # 7  (barrier of the conventional fuser)
+        Gate("RZZ", (0, 3), 0.8),      # 8
+        Gate("CPHASE", (1, 3), 0.9),   # 9
+        Gate("RX", (1,), 1.0),         # 10 (touches the run: deferred, marks qubit 1)
+        Gate("RZZ", (1, 4), 1.1),      # 11 (touches a marked qubit: stops the run)
+    ]
+
+
+def conventional_diag_fusion(gates):
+    """Fuses only runs of adjacent diagonal gates (stops at the first
+    non-diagonal gate); returns the list of runs' qubit sets and sizes."""
+    runs, cur = [], []
+    for g in gates:
+        if g.kind in W.DIAGONAL_KINDS:
+            cur.append(g)
+        else:
+            if cur:
+                runs.append(cur)
+            cur = []
+    if cur:
+        runs.append(cur)
+    return [(sorted(set(q for g in r for q in g.qubits)), len(r)) for r in runs]
+
+
+def test_diagonal_detector_figure4(oracle_mod):
+    n = 5
+    gates = figure4_circuit()
+    p = qsim.Plan(n, gates, opt=qsim.OPT_DIAG)
+    ops = p.ops()
+    diags = [o for o in ops if o["kind"] == "DIAG"]
+    # one 4-qubit fused diagonal from RZZ2, RZZ5, CP6, RZZ8, CP9 and RZZ11 alone
+    assert [d["qubits"] for d in diags] == [[0, 1, 2, 3], [1, 4]]
+    # gates after the prefix: H3, RY4, RX7, D4, RX10, RZZ11 -> 6 ops
+    assert len([o for o in ops if o["kind"] in ("DENSE", "DIAG")]) == 5 + 6
+    # conventional fusion: RZZ5+CP6 and RZZ8+CP9 are two 3-qubit runs
+    runs = conventional_diag_fusion(gates[5:])
+    assert ([1, 2, 3], 2) in runs and ([0, 1, 3], 2) in runs
+    assert max(len(q) for q, _ in runs) == 3
+    want = oracle_mod.run(n, gates)
+    got = run_plan(ops, n, p.layout())
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_diagonal_detector_respects_D(oracle_mod):
+    n = 12
+    gates = W.hadamard_diagonal_circuit(n, 200, seed=7)
+    for D in (2, 4, 7, 12):
+        p = qsim.Plan(n, gates, opt=qsim.OPT_DIAG, D=D)
+        ops = p.ops()
+        assert all(len(o["qubits"]) <= max(D, 2) for o in ops if o["kind"] == "DIAG")
+        got = run_plan(ops, n, p.layout())
+        assert np.max(np.abs(got - oracle_mod.run(n, gates))) < 1e-12
+
+
+def test_diagonal_detector_visits_each_gate_once():
+    """Sec. 4.5: every gate is placed exactly once, O(G)."""
+    for n, g in ((20, W.diag_heavy(20, 500, 1)), (16, W.layered(16, 10, 2)), (10, W.random_mixed(10, 300, 3))):
+        p = qsim.Plan(n, g, opt=qsim.OPT_DIAG)
+        assert p.counters()["dd_visits"] == len(g)
+
+
+# ---------------------------------------------------------------- merge booster (Sec. 4.4)
+def worked_example_circuit():
+    """8 qubits, 40 gates, with entanglement-free blocks of 6, 6, 7, 7 gates on
+    the 2-qubit groups, 7 and 4 on the 4-qubit groups and 3 on all 8 (the
+    per-block counts of the paper's example; the figure's circuit itself is
+    not available)."""
+    leaf = lambda a, b, extra: [Gate("H", (a,)), Gate("H", (b,)), Gate("CNOT", (a, b)), Gate("RZ", (a,), 0.3),
+                                Gate("RX", (b,), 0.4), Gate("CZ", (a, b))] + extra
+    g = leaf(0, 1, []) + leaf(2, 3, []) + leaf(4, 5, [Gate("RY", (4,), 0.5)]) + leaf(6, 7, [Gate("RY", (6,), 0.6)])
+    g += [Gate("CNOT", (1, 2)), Gate("RX", (1,), 0.1), Gate("RX", (2,), 0.2), Gate("CZ", (0, 3)), Gate("H", (0,)),
+          Gate("H", (3,)), Gate("CNOT", (0, 2))]
+    g += [Gate("CNOT", (5, 6)), Gate("RX", (5,), 0.7), Gate("RY", (6,), 0.8), Gate("CZ", (4, 7))]
+    g += [Gate("CNOT", (3, 4)), Gate("H", (3,)), Gate("CZ", (0, 7))]
+    assert len(g) == 40
+    return g
+
+
+def test_booster_worked_example_counts(oracle_mod):
+    """Sec. 4.4: 1,336 state accesses with the booster vs 40 x 2^8 = 10,240."""
+    n = 8
+    gates = worked_example_circuit()
+    plain = qsim.Plan(n, gates, opt=0).ops()
+    assert access_count(plain) == 40 * 2 ** 8 == 10240
+    p = qsim.Plan(n, gates, opt=qsim.OPT_BOOST, B=4)
+    ops = p.ops()
+    assert access_count(ops) == (6 + 6 + 7 + 7) * 4 + (7 + 4) * 16 + 3 * 256 + 2 * 16 + 256 == 1336
+    assert [o["buffer_qubits"] for o in ops if o["kind"] == "KRON"] == [4, 4, 8]
+    assert np.max(np.abs(run_plan(ops, n, p.layout()) - oracle_mod.run(n, gates))) < 1e-13
+
+
+def divider_leaves(n, B):
+    """Leaf sizes of the plan's booster: sizes of the INIT'ed sub-states."""
+    ops = qsim.Plan(n, [Gate("H", (0,))], opt=qsim.OPT_BOOST, B=B).ops()
+    return [o["buffer_qubits"] for o in ops if o["kind"] == "INIT" and o["buffer"] != 0]
+
+
+def test_divider_pins():
+    for B in range(3, 8):
+        assert divider_leaves(8, B) == [2, 2, 2, 2]  # ceil(8/B) = 2 or 3
+    assert divider_leaves(30, 4) == [7, 8, 7, 8]
+    assert divider_leaves(28, 4) == [7, 7, 7, 7]
+    assert divider_leaves(5, 3) == [2, 1, 2]
+
+
+def test_divider_32_qubits_two_16_halves():
+    """Sec. 4.4: for 32 qubits the largest blocks are two 2^16 sub-states."""
+    for B in range(2, 9):
+        ops = qsim.Plan(32, [Gate("H", (0,))], opt=qsim.OPT_BOOST, B=B).ops()
+        krons = [o for o in ops if o["kind"] == "KRON"]
+        last = krons[-1]
+        assert last["buffer"] == 0 and last["buffer_qubits"] == 32
+        sizes = {o["buffer"]: o["buffer_qubits"] for o in ops if o["kind"] in ("INIT", "KRON")}
+        assert sizes[last["src_lo"]] == 16 and sizes[last["src_hi"]] == 16
+
+
+def test_booster_odd_queue_keeps_every_qubit(oracle_mod):
+    """An unpaired trailing group is carried over (the literal listing would
+    drop it): N=5, B=3 divides as [2, 1, 2]."""
+    n = 5
+    gates = W.random_mixed(n, 60, seed=4, max_k=2)
+    p = qsim.Plan(n, gates, opt=qsim.OPT_BOOST, B=3)
+    ops = p.ops()
+    assert np.max(np.abs(run_plan(ops, n, p.layout()) - oracle_mod.run(n, gates))) < 1e-13
+
+
+@pytest.mark.parametrize("n,B", [(n, B) for n in (4, 6, 9, 12, 13) for B in (2, 3, 4, 6)])
+def test_booster_product_prefix(oracle_mod, n, B):
+    gates = W.product_circuit(n, 3, seed=n) + W.layered(n, 2, seed=B)
+    p = qsim.Plan(n, gates, opt=qsim.OPT_BOOST | qsim.OPT_STAGES | qsim.OPT_FUSE, B=B, C=min(10, n))
+    ops = p.ops()
+    assert np.max(np.abs(run_plan(ops, n, p.layout()) - oracle_mod.run(n, gates))) < 1e-12
+
+
+def test_booster_linear_gate_accounting():
+    """Sec. 4.4 complexity: the booster visits the gates of the circuit a
+    bounded number of times per merge level (O(G) per level, log N levels)."""
+    for n in (16, 24, 30):
+        g = W.layered(n, 5, 1)
+        p = qsim.Plan(n, g, opt=qsim.OPT_BOOST)
+        c = p.counters()
+        assert c["booster_gates"] <= len(g)
+        assert c["booster_groups"] >= 2
+
+
+def test_plan_time_small_fraction():
+    """Sec. 4.2: the optimiser stays polynomial and cheap; the 30-qubit
+    layered plan takes well under a second on the host."""
+    n, g = W.config_circuit("layered30")
+    p = qsim.Plan(n, g, opt=qsim.OPT_ALL)
+    assert p.stats()["plan_ms"] < 1000
+
+
+def test_invalid_gates_rejected():
+    with pytest.raises(qsim.QsimError):
+        qsim.Plan(3, [Gate("H", (3,))])
+    with pytest.raises(qsim.QsimError):
+        qsim.Plan(3, [Gate("CZ", (1, 1))])
+    with pytest.raises(qsim.QsimError):
+        qsim.Plan(3, [Gate("U", (0,), 0.0, np.array([[1, 1], [0, 1]], dtype=complex))])
+    with pytest.raises(qsim.QsimError):
+        qsim.Plan(3, [Gate("DIAG", (0,), 0.0, np.array([1, 2], dtype=complex))])

@@ -172,9 +172,12 @@ sim_status sim_destroy(sim_ctx *ctx);
 
 /* ---- batched small circuits (serving) --------------------------------------
  * Run several contexts whose states are small (N <= 13 for C128, N <= 14 for
- * C64) in ONE launch on `stream`: one workgroup per circuit keeps the whole
- * state on chip, applies the whole gate list and writes the final state to
- * the context's buffer.  Each context must have a loaded circuit.  Results
+ * C64) in ONE launch per 128 contexts on `stream` (NULL: the first context's
+ * stream): one workgroup per circuit keeps the whole state in LDS, applies
+ * the whole gate list from |0...0> and writes the final state to the
+ * context's buffer.  All contexts need a loaded circuit and the same dtype
+ * (SIM_E_INVAL otherwise; SIM_E_UNSUPPORTED for a state that is too large).
+ * Does not wait: synchronise `stream` before reading the states.  Results
  * equal those of sim_run on each context alone, up to rounding order. */
 sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream);
 
@@ -236,6 +239,11 @@ sim_status sim_plan_stats(const sim_plan *plan, sim_run_stats *out);
 sim_status sim_plan_counters(const sim_plan *plan, uint64_t *dd_visits, uint64_t *booster_gates,
                              uint64_t *booster_groups);
 sim_status sim_plan_destroy(sim_plan *plan);
+
+/* Plain device-to-device copy of `bytes` (a multiple of 16) on `stream`: the
+ * achievable-HBM-bandwidth reference the benchmark reports next to the peak.
+ * Device pointers; does not synchronise. */
+sim_status sim_device_copy(void *dst, const void *src, uint64_t bytes, void *stream);
 
 /* Library version string. */
 const char *sim_version(void);

@@ -29,6 +29,7 @@ struct Prepared {
     int C = 0, nph = 0;
     uint64_t nchunks = 0;
     bool small = false;         // STAGE run by the small-state kernel
+    bool mfma = false;          // DENSE on the matrix cores (table holds the real-ified matrix)
     uint32_t item = 0;          // index of its SmallItem
     uint32_t batch = 0;         // ops of the batch starting here (0 = inside a batch)
 };
@@ -77,10 +78,8 @@ struct sim_ctx {
     DevBuf tables, prog, gdesc, items, scratch, io;
     std::vector<DevBuf> subbufs;          // booster sub-states (index = buffer id)
     std::vector<Prepared> prep;
-    std::vector<qs::SmallItem> host_items; // for batched serving launches
-    std::vector<qs::GateDesc> host_gdesc;
-    uint32_t small_n = 0;                  // whole-circuit small program (serving)
-    bool small_whole = false;
+    std::vector<qs::SmallItem> host_items;
+    bool small_whole = false;              // whole circuit as one small-state item (batched runs)
     size_t small_whole_item = 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -159,14 +158,12 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
         w[pb + 0] = (uint32_t)ph.ops.size();
         w[pb + 1] = nonr;
         w[pb + 2] = rmask;
+        if ((int)ph.tmap.size() != C - reg_bits) throw std::runtime_error("encode_stage: bad thread map");
+        for (size_t i = 0; i < ph.tmap.size(); ++i) w[pb + 4 + i / 4] |= (uint32_t)ph.tmap[i] << (8 * (i % 4));
         std::vector<int> reg_phys;
         for (int i : ph.reg) reg_phys.push_back(st.local[i]);
         uint64_t lane_phys = 0;
-        for (int i = 0, cnt = 0; i < C && cnt < 6; ++i)
-            if (!((rmask >> i) & 1)) {
-                lane_phys |= 1ull << st.local[i];
-                ++cnt;
-            }
+        for (int i = 0; i < 6; ++i) lane_phys |= 1ull << st.local[ph.tmap[i]];
         for (size_t o = 0; o < ph.ops.size(); ++o) {
             const qs::KOp &k = ph.ops[o];
             uint32_t *op = &w[pb + 16 + 32 * o];
@@ -188,6 +185,10 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
             } else {
                 op[0] = 2;
                 op[1] = (uint32_t)k.dq.size();
+                bool uni = true;
+                for (int t : k.dq)
+                    if ((lane_phys >> t) & 1) uni = false;
+                op[3] = uni ? 1u : 0u;
                 if (k.dq.size() > 24) throw std::runtime_error("encode_stage: diagonal too wide");
                 for (int j = 0; j < (1 << reg_bits); ++j) {
                     uint32_t y = 0;
@@ -259,8 +260,25 @@ sim_status prepare(sim_ctx *c)
         case SIM_OP_DENSE:
         case SIM_OP_DIAG: {
             const uint64_t toff = tables.size();
-            if (op.op.diag) tables.insert(tables.end(), op.op.m.begin(), op.op.m.end());
-            else tables.insert(tables.end(), op.op.m.begin(), op.op.m.end());
+            const int k = op.op.k();
+            if (!op.op.diag && (k == 4 || k == 5) && op.buffer_qubits >= k + 4) {
+                // real-ified 2^(k+1) x 2^(k+1) matrix for the MFMA kernel,
+                // stored as consecutive pairs of reals
+                const int d = 1 << k, D = 2 * d;
+                std::vector<double> mr((size_t)D * D);
+                for (int r = 0; r < d; ++r)
+                    for (int c = 0; c < d; ++c) {
+                        const cplx u = op.op.m[(size_t)r * d + c];
+                        mr[(size_t)(2 * r) * D + 2 * c] = u.real();
+                        mr[(size_t)(2 * r) * D + 2 * c + 1] = -u.imag();
+                        mr[(size_t)(2 * r + 1) * D + 2 * c] = u.imag();
+                        mr[(size_t)(2 * r + 1) * D + 2 * c + 1] = u.real();
+                    }
+                for (size_t i = 0; i < mr.size(); i += 2) tables.push_back(cplx(mr[i], mr[i + 1]));
+                p.mfma = true;
+            } else {
+                tables.insert(tables.end(), op.op.m.begin(), op.op.m.end());
+            }
             p.gd = desc_of(op.op, toff);
             break;
         }
@@ -293,6 +311,23 @@ sim_status prepare(sim_ctx *c)
             return fail(c, SIM_E_UNSUPPORTED, "plan op kind not executable");
         }
         c->prep.push_back(p);
+    }
+    // the whole circuit as one small-state item, for batched launches of
+    // many small circuits (sim_run_batch)
+    c->small_whole = c->n <= small_max;
+    if (c->small_whole) {
+        qs::SmallItem it{};
+        it.n = (uint32_t)c->n;
+        it.ngates = (uint32_t)c->gates.size();
+        it.init = 1;
+        it.state = c->state;
+        item_gate_off.push_back(gdesc.size());
+        for (const qs::Operator &g : c->gates) {
+            gdesc.push_back(desc_of(g, tables.size()));
+            tables.insert(tables.end(), g.m.begin(), g.m.end());
+        }
+        c->small_whole_item = items.size();
+        items.push_back(it);
     }
     // batches of consecutive small runs on distinct buffers
     for (size_t i = 0; i < c->prep.size();) {
@@ -369,8 +404,12 @@ sim_status execute(sim_ctx *c)
             break;
         }
         case SIM_OP_DENSE:
-            e = qs::launch_dense<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp,
-                                    c->stream);
+            if (p.mfma)
+                e = qs::launch_dense_mfma<R>(c->buf(p.buffer), p.nb, p.gd,
+                                             (const char *)c->tables.p + p.gd.table * amp, c->stream);
+            else
+                e = qs::launch_dense<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp,
+                                        c->stream);
             break;
         case SIM_OP_DIAG:
             e = qs::launch_diag_q<R>(c->buf(p.buffer), p.nb, (int)p.gd.k, p.gd.q,
@@ -427,6 +466,12 @@ void fill_stats(const qs::Plan &P, uint64_t n_gates, sim_run_stats *s)
 extern "C" {
 
 const char *sim_version(void) { return "qsim355 0.1 (gfx950)"; }
+
+sim_status sim_device_copy(void *dst, const void *src, uint64_t bytes, void *stream)
+{
+    if (!dst || !src || (bytes % 16)) return SIM_E_INVAL;
+    return qs::launch_copy(dst, src, bytes, (hipStream_t)stream) == hipSuccess ? SIM_OK : SIM_E_DEVICE;
+}
 
 sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts, sim_ctx **out)
 {
@@ -693,8 +738,33 @@ sim_status sim_destroy(sim_ctx *c)
 sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream)
 {
     if (!ctxs && n_ctx) return SIM_E_INVAL;
-    (void)stream;
-    return SIM_E_UNSUPPORTED;
+    if (n_ctx == 0) return SIM_OK;
+    for (uint32_t i = 0; i < n_ctx; ++i) {
+        sim_ctx *c = ctxs[i];
+        if (!c) return SIM_E_INVAL;
+        if (!c->loaded) return fail(c, SIM_E_STATE, "no circuit loaded");
+        if (!c->small_whole) return fail(c, SIM_E_UNSUPPORTED, "state too large for a batched small-state run");
+        if (c->dtype != ctxs[0]->dtype) return fail(c, SIM_E_INVAL, "batched contexts must share the dtype");
+    }
+    hipStream_t s = stream ? (hipStream_t)stream : ctxs[0]->stream;
+    for (uint32_t i0 = 0; i0 < n_ctx; i0 += qs::kSmallBatchMax) {
+        const uint32_t cnt = std::min<uint32_t>(qs::kSmallBatchMax, n_ctx - i0);
+        qs::SmallPtrs P{};
+        uint32_t maxn = 0;
+        for (uint32_t u = 0; u < cnt; ++u) {
+            sim_ctx *c = ctxs[i0 + u];
+            P.item[u] = (const qs::SmallItem *)c->items.p + c->small_whole_item;
+            maxn = std::max<uint32_t>(maxn, (uint32_t)c->n);
+        }
+        hipError_t e = ctxs[0]->dtype == SIM_C128 ? qs::launch_small_ptrs<double>(P, cnt, maxn, s)
+                                                  : qs::launch_small_ptrs<float>(P, cnt, maxn, s);
+        if (e != hipSuccess) return hip_fail(ctxs[0], e, "batched launch");
+    }
+    for (uint32_t i = 0; i < n_ctx; ++i) {
+        ctxs[i]->ran = true;
+        ctxs[i]->timing_pending = false;
+    }
+    return SIM_OK;
 }
 
 // ---- host-only planning ----------------------------------------------------

@@ -4,8 +4,29 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace qs {
+
+// Read-only data every lane of a wave reads at the same address (gate
+// matrices, stage programs) is addressed through the constant address space,
+// so the compiler issues scalar loads for it.
+#define QS_CONST __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ const QS_CONST T *as_const(const T *p)
+{
+    return (const QS_CONST T *)(p);
+}
+
+// Complex entry i of an interleaved (re, im) real array, in any address space.
+template <typename R, typename P>
+__device__ __forceinline__ auto ldc(P m, uint64_t i)
+{
+    using V = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
+    V v;
+    v.x = m[2 * i];
+    v.y = m[2 * i + 1];
+    return v;
+}
 
 // Interleaved complex amplitude: double2 (complex128) or float2 (complex64).
 template <typename R> struct C2;
@@ -73,6 +94,11 @@ struct SmallItem {           // one circuit of a batched small-state launch
     uint32_t pad;
 };
 
+constexpr int kSmallBatchMax = 128;
+struct SmallPtrs {           // kernel-argument list of items for one batched launch
+    const SmallItem *item[kSmallBatchMax];
+};
+
 // ---- launchers (return hipError_t of the launch) ---------------------------
 template <typename R> hipError_t launch_init(void *state, int n, hipStream_t s);
 template <typename R> hipError_t launch_dense(void *state, int n, const GateDesc &g, const void *mat, hipStream_t s);
@@ -90,6 +116,8 @@ template <typename RA, typename RB> hipError_t launch_inner(const void *a, const
 size_t inner_scratch_bytes(int n);
 template <typename R> hipError_t launch_small_batch(const SmallItem *items_dev, uint32_t count, uint32_t max_n,
                                                     hipStream_t s);
+template <typename R> hipError_t launch_small_ptrs(const SmallPtrs &P, uint32_t count, uint32_t max_n,
+                                                   hipStream_t s);
 int small_max_qubits(bool c128);
 
 // Stage kernel: program built by the executor (see kernel_stage.hip).

@@ -69,6 +69,7 @@ struct KOp {
 
 struct Phase {
     std::vector<int> reg;             // local bit index of register bit b
+    std::vector<int> tmap;            // local bit index of thread-id bit i (lanes = i < 6)
     std::vector<KOp> ops;
 };
 

@@ -1,0 +1,124 @@
+// Dense k-qubit gate (k = 4, 5) on the matrix cores: a batched GEMM.
+//
+// For every group of 2^k amplitudes that differ only in the gate's qubits
+// (Sec. 2.2), y = U x.  Written in real arithmetic on interleaved (re, im)
+// vectors, y_r = M_r x_r with the 2^(k+1) x 2^(k+1) real matrix
+//   M_r[2r][2c] = Re U[r][c],  M_r[2r][2c+1] = -Im U[r][c],
+//   M_r[2r+1][2c] = Im U[r][c], M_r[2r+1][2c+1] = Re U[r][c],
+// so a wave computes Y = M_r X for 16 groups at once (X: 2^(k+1) x 16) with
+// 16x16x4 MFMA steps: complex64 states on FP32 MFMA, complex128 on FP64 MFMA.
+//
+// Operand layout of the 16x16x4 MFMA (one block): lane l = j + 16 q holds
+// A[j][q] and B[q][j] of each k-step, and D[4q + v][j] in accumulator v.
+// Every lane keeps its slice of M_r in registers for the whole launch.
+#include "device.hpp"
+
+namespace qs {
+
+namespace {
+
+constexpr int kMfmaThreads = 256;
+
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename R, int K>
+__global__ __launch_bounds__(kMfmaThreads) void k_dense_mfma(c2_t<R> *__restrict__ a, const R *__restrict__ mr,
+                                                             uint64_t nbatches, GateDesc g)
+{
+    using V = c2_t<R>;
+    using acc_t = typename Mfma<R>::acc_t;
+    constexpr int D = 2 << K;   // real dimension
+    constexpr int T = D / 16;   // 16-row output tiles
+    constexpr int S = D / 4;    // k-steps of 4
+    const uint32_t lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+
+    R areg[T][S];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int s = 0; s < S; ++s) areg[t][s] = mr[(16 * t + j) * D + 4 * s + q];
+
+    // amplitude offset of matrix index c (bit t of c <-> qubit q[t])
+    auto off = [&](int c) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+            if ((c >> t) & 1) o |= 1ull << g.q[t];
+        return o;
+    };
+    uint64_t in_off[S];   // B row 4s + q -> amplitude 2s + q/2, part q%2
+#pragma unroll
+    for (int s = 0; s < S; ++s) in_off[s] = off(2 * s + (int)(q >> 1));
+    uint64_t out_off[T][2];  // D rows 16t + 4q + v -> amplitudes 8t + 2q + v/2
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        out_off[t][0] = off(8 * t + 2 * (int)q);
+        out_off[t][1] = off(8 * t + 2 * (int)q + 1);
+    }
+
+    const uint64_t wave = ((uint64_t)blockIdx.x * kMfmaThreads + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kMfmaThreads) >> 6;
+    for (uint64_t b = wave; b < nbatches; b += nwaves) {
+        const uint64_t base = insert_zeros<K>(b * 16 + j, g.sorted);
+        R bv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const V v = a[base | in_off[s]];
+            bv[s] = (q & 1) ? v.y : v.x;
+        }
+        acc_t acc[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            acc[t] = acc_t{R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int s = 0; s < S; ++s) acc[t] = Mfma<R>::mma(areg[t][s], bv[s], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            V y0, y1;
+            y0.x = acc[t][0];
+            y0.y = acc[t][1];
+            y1.x = acc[t][2];
+            y1.y = acc[t][3];
+            a[base | out_off[t][0]] = y0;
+            a[base | out_off[t][1]] = y1;
+        }
+    }
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_dense_mfma(void *state, int n, const GateDesc &g, const void *mat, hipStream_t s)
+{
+    const int k = (int)g.k;
+    if ((k != 4 && k != 5) || n < k + 4) return hipErrorInvalidValue;
+    const uint64_t nbatches = 1ull << (n - k - 4);
+    const uint64_t waves_per_block = kMfmaThreads / 64;
+    uint64_t blocks = (nbatches + waves_per_block - 1) / waves_per_block;
+    if (blocks > 8192) blocks = 8192;
+    auto *a = (c2_t<R> *)state;
+    auto *m = (const R *)mat;
+    if (k == 4) k_dense_mfma<R, 4><<<(uint32_t)blocks, kMfmaThreads, 0, s>>>(a, m, nbatches, g);
+    else k_dense_mfma<R, 5><<<(uint32_t)blocks, kMfmaThreads, 0, s>>>(a, m, nbatches, g);
+    return hipGetLastError();
+}
+
+template hipError_t launch_dense_mfma<float>(void *, int, const GateDesc &, const void *, hipStream_t);
+template hipError_t launch_dense_mfma<double>(void *, int, const GateDesc &, const void *, hipStream_t);
+
+}  // namespace qs

@@ -19,9 +19,10 @@
 //   header  [0] C  [1] n  [2] nphases  [3] RB  [4,5] local mask  [6,7] global mask
 //           [8 + i] physical bit of local bit i (i < C)   [32 + p] word offset of phase p
 //   phase   [0] nops  [1] non-register local mask  [2] register local mask
+//           [4..7] local bit of thread-id bit i (bytes; bits 0..5 are the lane bits)
 //           [16 + 32 o ...] op o
 //   op      [0] type (1 dense, 2 diagonal)  [1] register mask | diagonal size
-//           [2] selector count  [3] selector wave-uniform  [4,5] table offset
+//           [2] selector count  [3] selector / table index wave-uniform  [4,5] table offset
 //           [8..15] bit positions (bytes)  [16..31] diagonal: register index part (u16)
 #include "device.hpp"
 
@@ -44,7 +45,10 @@ template <> __device__ __forceinline__ uint32_t swz<float>(uint32_t i)
     return i ^ (((i >> 5) ^ (i >> 10)) & 31u);
 }
 
-__device__ __forceinline__ uint32_t byte_at(const uint32_t *w, int i) { return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
+__device__ __forceinline__ uint32_t byte_at(const QS_CONST uint32_t *w, int i)
+{
+    return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+}
 
 template <int RB>
 __device__ __forceinline__ void reg_positions(uint32_t rmask, int *pos)
@@ -68,8 +72,8 @@ __device__ __forceinline__ uint32_t reg_offset(int j, const int *pos)
 
 // Dense operator on the register bits of MASK; m holds (2^k)^2 entries,
 // bit t of its index <-> t-th set bit of MASK.
-template <typename R, int RB, int MASK>
-__device__ __forceinline__ void apply_dense(c2_t<R> *amp, const c2_t<R> *__restrict__ m)
+template <typename R, int RB, int MASK, typename MP>
+__device__ __forceinline__ void apply_dense(c2_t<R> *amp, MP m)
 {
     using V = c2_t<R>;
     constexpr int K = __builtin_popcount(MASK);
@@ -95,40 +99,38 @@ __device__ __forceinline__ void apply_dense(c2_t<R> *amp, const c2_t<R> *__restr
         for (int c = 0; c < D; ++c) v[c] = amp[idx[c]];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            V acc;
-            acc.x = R(0);
-            acc.y = R(0);
+            V acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
 #pragma unroll
-            for (int c = 0; c < D; ++c) cmac(acc, m[r * D + c], v[c]);
+            for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
             amp[idx[r]] = acc;
         }
     }
 }
 
-template <typename R, int RB>
-__device__ __forceinline__ void dispatch_dense(uint32_t mask, c2_t<R> *amp, const c2_t<R> *m)
+template <typename R, int RB, typename MP>
+__device__ __forceinline__ void dispatch_dense(uint32_t mask, c2_t<R> *amp, MP m)
 {
     constexpr int FULL = (1 << RB) - 1;
     switch (mask) {
-    case 1: apply_dense<R, RB, 1>(amp, m); break;
-    case 2: apply_dense<R, RB, 2>(amp, m); break;
-    case 4: apply_dense<R, RB, 4>(amp, m); break;
-    case 8: apply_dense<R, RB, 8>(amp, m); break;
-    case 3: apply_dense<R, RB, 3>(amp, m); break;
-    case 5: apply_dense<R, RB, 5>(amp, m); break;
-    case 6: apply_dense<R, RB, 6>(amp, m); break;
-    case 9: apply_dense<R, RB, 9>(amp, m); break;
-    case 10: apply_dense<R, RB, 10>(amp, m); break;
-    case 12: apply_dense<R, RB, 12>(amp, m); break;
-    case FULL: apply_dense<R, RB, FULL>(amp, m); break;
+    case 1: apply_dense<R, RB, 1, MP>(amp, m); break;
+    case 2: apply_dense<R, RB, 2, MP>(amp, m); break;
+    case 4: apply_dense<R, RB, 4, MP>(amp, m); break;
+    case 8: apply_dense<R, RB, 8, MP>(amp, m); break;
+    case 3: apply_dense<R, RB, 3, MP>(amp, m); break;
+    case 5: apply_dense<R, RB, 5, MP>(amp, m); break;
+    case 6: apply_dense<R, RB, 6, MP>(amp, m); break;
+    case 9: apply_dense<R, RB, 9, MP>(amp, m); break;
+    case 10: apply_dense<R, RB, 10, MP>(amp, m); break;
+    case 12: apply_dense<R, RB, 12, MP>(amp, m); break;
+    case FULL: apply_dense<R, RB, FULL, MP>(amp, m); break;
     default:
         if constexpr (RB == 5) {
             switch (mask) {
-            case 16: apply_dense<R, RB, 16>(amp, m); break;
-            case 17: apply_dense<R, RB, 17>(amp, m); break;
-            case 18: apply_dense<R, RB, 18>(amp, m); break;
-            case 20: apply_dense<R, RB, 20>(amp, m); break;
-            case 24: apply_dense<R, RB, 24>(amp, m); break;
+            case 16: apply_dense<R, RB, 16, MP>(amp, m); break;
+            case 17: apply_dense<R, RB, 17, MP>(amp, m); break;
+            case 18: apply_dense<R, RB, 18, MP>(amp, m); break;
+            case 20: apply_dense<R, RB, 20, MP>(amp, m); break;
+            case 24: apply_dense<R, RB, 24, MP>(amp, m); break;
             default: break;
             }
         }
@@ -136,31 +138,42 @@ __device__ __forceinline__ void dispatch_dense(uint32_t mask, c2_t<R> *amp, cons
     }
 }
 
+// Local index of thread-id bits under a phase's thread map.
+__device__ __forceinline__ uint32_t thread_local_base(uint32_t tid, const QS_CONST uint32_t *tmap, int nbits)
+{
+    uint32_t lb = 0;
+    for (int i = 0; i < nbits; ++i)
+        if ((tid >> i) & 1) lb |= 1u << byte_at(tmap, i);
+    return lb;
+}
+
+// Moves the chunk between two register/thread mappings through LDS.
 template <typename R, int RB>
-__device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t tid, uint32_t old_nonr,
-                                          uint32_t old_r, uint32_t new_nonr, uint32_t new_r)
+__device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t old_lb, uint32_t old_r,
+                                          uint32_t new_lb, uint32_t new_r)
 {
     constexpr int NR = 1 << RB;
     int pos[RB];
     __syncthreads();
     reg_positions<RB>(old_r, pos);
-    const uint32_t lb = (uint32_t)deposit(tid, old_nonr);
 #pragma unroll
-    for (int j = 0; j < NR; ++j) lds[swz<R>(lb | reg_offset<RB>(j, pos))] = amp[j];
+    for (int j = 0; j < NR; ++j) lds[swz<R>(old_lb | reg_offset<RB>(j, pos))] = amp[j];
     __syncthreads();
     reg_positions<RB>(new_r, pos);
-    const uint32_t nb = (uint32_t)deposit(tid, new_nonr);
 #pragma unroll
-    for (int j = 0; j < NR; ++j) amp[j] = lds[swz<R>(nb | reg_offset<RB>(j, pos))];
+    for (int j = 0; j < NR; ++j) amp[j] = lds[swz<R>(new_lb | reg_offset<RB>(j, pos))];
 }
 
 template <typename R, int RB>
 __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
-                                                            const uint32_t *__restrict__ P,
+                                                            const uint32_t *__restrict__ Pg,
                                                             const c2_t<R> *__restrict__ tables,
                                                             uint64_t nchunks)
 {
     using V = c2_t<R>;
+    const QS_CONST uint32_t *P = as_const(Pg);
+    const QS_CONST R *ctables = as_const(reinterpret_cast<const R *>(tables));
+    const R *rtables = reinterpret_cast<const R *>(tables);
     constexpr int NR = 1 << RB;
     extern __shared__ char smem_raw[];
     V *lds = reinterpret_cast<V *>(smem_raw);
@@ -177,6 +190,9 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
 #pragma unroll
     for (int b = 0; b < RB; ++b) regphys[b] = 1ull << P[8 + C - RB + b];
     const uint64_t tphys = deposit(tid, Lmask);
+    // load/store mapping: thread-id bit i <-> local bit i (packed like a phase's map)
+    uint32_t neutral_t[3] = {0, 0, 0};
+    for (int i = 0; i < C - RB; ++i) neutral_t[i / 4] |= (uint32_t)i << (8 * (i % 4));
 
     V amp[NR];
     for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
@@ -192,18 +208,26 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
                 amp[j] = state[o];
             }
         }
-        uint32_t cur_nonr = neutral_nonr, cur_r = neutral_r;
+        // current mapping: register mask and thread-map words (workgroup-uniform)
+        uint32_t cur_lb = tid, cur_r = neutral_r;
+        uint32_t cur_t0 = neutral_t[0], cur_t1 = neutral_t[1], cur_t2 = neutral_t[2];
         for (int p = 0; p < nph; ++p) {
-            const uint32_t *ph = P + P[32 + p];
-            const uint32_t nops = ph[0], nonr = ph[1], rmask = ph[2];
-            if (rmask != cur_r) {
-                transpose<R, RB>(amp, lds, tid, cur_nonr, cur_r, nonr, rmask);
-                cur_nonr = nonr;
+            const QS_CONST uint32_t *ph = P + P[32 + p];
+            const uint32_t nops = ph[0], rmask = ph[2];
+            const uint32_t t0 = ph[4], t1 = ph[5], t2 = ph[6];
+            if (rmask != cur_r || t0 != cur_t0 || t1 != cur_t1 || t2 != cur_t2) {
+                const uint32_t lb = thread_local_base(tid, ph + 4, C - RB);
+                transpose<R, RB>(amp, lds, cur_lb, cur_r, lb, rmask);
+                cur_lb = lb;
                 cur_r = rmask;
+                cur_t0 = t0;
+                cur_t1 = t1;
+                cur_t2 = t2;
             }
-            const uint64_t phys_base = cbase | deposit(deposit(tid, nonr), Lmask);
+            const uint32_t lb = cur_lb;
+            const uint64_t phys_base = cbase | deposit(lb, Lmask);
             for (uint32_t o = 0; o < nops; ++o) {
-                const uint32_t *op = ph + 16 + 32 * o;
+                const QS_CONST uint32_t *op = ph + 16 + 32 * o;
                 const uint64_t toff = (uint64_t)op[4] | ((uint64_t)op[5] << 32);
                 if (op[0] == 1u) {
                     const uint32_t mask = op[1], nsel = op[2];
@@ -212,11 +236,11 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
                         sel |= (uint32_t)((phys_base >> byte_at(op + 8, (int)u)) & 1ull) << u;
                     const int k = __builtin_popcount(mask);
                     const uint32_t msz = 1u << (2 * k);
-                    if (op[3]) {
+                    if (op[3]) {  // block selector constant across the wave: scalar loads
                         sel = __builtin_amdgcn_readfirstlane(sel);
-                        dispatch_dense<R, RB>(mask, amp, tables + toff + (uint64_t)sel * msz);
-                    } else {
-                        dispatch_dense<R, RB>(mask, amp, tables + toff + (uint64_t)sel * msz);
+                        dispatch_dense<R, RB>(mask, amp, ctables + 2 * (toff + (uint64_t)sel * msz));
+                    } else {      // selector varies by lane: per-lane loads
+                        dispatch_dense<R, RB>(mask, amp, rtables + 2 * (toff + (uint64_t)sel * msz));
                     }
                 } else {
                     const uint32_t nd = op[1];
@@ -232,7 +256,8 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
                 }
             }
         }
-        if (cur_r != neutral_r) transpose<R, RB>(amp, lds, tid, cur_nonr, cur_r, neutral_nonr, neutral_r);
+        if (cur_r != neutral_r || cur_t0 != neutral_t[0] || cur_t1 != neutral_t[1] || cur_t2 != neutral_t[2])
+            transpose<R, RB>(amp, lds, cur_lb, cur_r, tid, neutral_r);
         {
             const uint64_t pb = cbase | tphys;
 #pragma unroll

@@ -26,10 +26,10 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_init(c2_t<R> *__restrict__ a, uint64_t len)
 {
     using V = c2_t<R>;
-    const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+    const uint64_t i0 = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const uint64_t i = i0 + u;
+        const uint64_t i = i0 + (uint64_t)u * kBlock;
         if (i < len) {
             V v;
             v.x = i == 0 ? R(1) : R(0);
@@ -43,10 +43,11 @@ __global__ __launch_bounds__(kBlock) void k_init(c2_t<R> *__restrict__ a, uint64
 // 2^k amplitudes that differ only in the gate's qubits are multiplied by the
 // gate matrix).  The matrix index is uniform across the wave.
 template <typename R, int K>
-__global__ __launch_bounds__(kBlock) void k_dense(c2_t<R> *__restrict__ a, const c2_t<R> *__restrict__ m,
+__global__ __launch_bounds__(kBlock) void k_dense(c2_t<R> *__restrict__ a, const c2_t<R> *__restrict__ mg,
                                                   uint64_t ngroups, GateDesc g)
 {
     using V = c2_t<R>;
+    const QS_CONST R *m = as_const(reinterpret_cast<const R *>(mg));
     constexpr int D = 1 << K;
     const uint64_t grp = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if (grp >= ngroups) return;
@@ -65,11 +66,9 @@ __global__ __launch_bounds__(kBlock) void k_dense(c2_t<R> *__restrict__ a, const
     for (int c = 0; c < D; ++c) v[c] = a[off[c]];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-        V acc;
-        acc.x = R(0);
-        acc.y = R(0);
+        V acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
 #pragma unroll
-        for (int c = 0; c < D; ++c) cmac(acc, m[r * D + c], v[c]);
+        for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
         a[off[r]] = acc;
     }
 }
@@ -101,9 +100,12 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_kron(c2_t<R> *__restrict__ dst, const c2_t<R> *__restrict__ lo,
                                                  const c2_t<R> *__restrict__ hi, int nlo, uint64_t len)
 {
-    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (x >= len) return;
-    dst[x] = cmul(lo[x & ((1ull << nlo) - 1)], hi[x >> nlo]);
+    const uint64_t x0 = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint64_t x = x0 + (uint64_t)u * kBlock;
+        if (x < len) dst[x] = cmul(lo[x & ((1ull << nlo) - 1)], hi[x >> nlo]);
+    }
 }
 
 // Qubit permutation (Sec. 2.3): dst[pi(x)] = src[x], pi moves source bit p to
@@ -139,11 +141,22 @@ __global__ __launch_bounds__(kBlock) void k_gather(const c2_t<R> *__restrict__ a
 // lane in increasing z, then a fixed butterfly over the lanes; a second
 // kernel adds the segments in order.
 struct MargArgs {
-    uint64_t smask, zmask;
+    uint64_t smask;
     int32_t nq, pad;
+    int32_t sorted[24];     // marginal qubits, ascending
     uint64_t zseg;          // z values per segment
     uint32_t nseg;
 };
+
+// deposit(z, ~S) for ascending S: insert a zero bit at every position of S.
+__device__ __forceinline__ uint64_t spread_out(uint64_t z, const MargArgs &M)
+{
+    for (int t = 0; t < M.nq; ++t) {
+        const uint64_t lo = z & ((1ull << M.sorted[t]) - 1);
+        z = ((z >> M.sorted[t]) << (M.sorted[t] + 1)) | lo;
+    }
+    return z;
+}
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_marg_partial(const c2_t<R> *__restrict__ a, MargArgs M,
@@ -158,13 +171,31 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const c2_t<R> *__restri
     double acc = 0.0;
     const uint64_t z0 = seg * M.zseg;
     for (uint64_t z = z0 + lane; z < z0 + M.zseg; z += 64) {
-        const c2_t<R> v = a[xy | deposit(z, M.zmask)];
+        const c2_t<R> v = a[xy | spread_out(z, M)];
         const double re = (double)v.x, im = (double)v.y;
         acc += re * re + im * im;
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) part[seg * nbins + y] = acc;
+}
+
+// Few bins, many segments: one block per bin, fixed strided sums then a
+// fixed tree.
+__global__ __launch_bounds__(kBlock) void k_marg_final_block(const double *__restrict__ part, uint64_t nbins,
+                                                             uint32_t nseg, double *__restrict__ out)
+{
+    __shared__ double sh[kBlock];
+    const uint64_t y = blockIdx.x;
+    double acc = 0.0;
+    for (uint32_t g = threadIdx.x; g < nseg; g += kBlock) acc += part[(uint64_t)g * nbins + y];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[y] = sh[0];
 }
 
 __global__ __launch_bounds__(kBlock) void k_marg_final(const double *__restrict__ part, uint64_t nbins,
@@ -236,8 +267,16 @@ __global__ __launch_bounds__(kBlock) void k_inner_final(const double2 *__restric
 
 __global__ __launch_bounds__(kBlock) void k_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, uint64_t n16)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * 4;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x; i < n16; i += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * kBlock < n16) v[u] = src[i + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * kBlock < n16) dst[i + u * kBlock] = v[u];
+    }
 }
 
 }  // namespace
@@ -286,7 +325,7 @@ template <typename R>
 hipError_t launch_kron(void *dst, const void *lo, int nlo, const void *hi, int nhi, hipStream_t s)
 {
     const uint64_t len = 1ull << (nlo + nhi);
-    k_kron<R><<<blocks_for(len, kBlock), kBlock, 0, s>>>((c2_t<R> *)dst, (const c2_t<R> *)lo,
+    k_kron<R><<<blocks_for(len, kBlock * 4), kBlock, 0, s>>>((c2_t<R> *)dst, (const c2_t<R> *)lo,
                                                          (const c2_t<R> *)hi, nlo, len);
     return hipGetLastError();
 }
@@ -338,8 +377,11 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
 {
     if (nq < 0 || nq > n || nq > 20) return hipErrorInvalidValue;
     MargArgs M{};
-    for (int t = 0; t < nq; ++t) M.smask |= 1ull << q[t];
-    M.zmask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~M.smask;
+    for (int t = 0; t < nq; ++t) {
+        M.smask |= 1ull << q[t];
+        M.sorted[t] = q[t];
+        if (t && q[t] <= q[t - 1]) return hipErrorInvalidValue;  // callers pass ascending qubits
+    }
     M.nq = nq;
     // y bit t <-> qubit q[t]: deposit() fills ascending positions, so the
     // bins come out in ascending-qubit order; the executor passes q sorted and
@@ -348,7 +390,10 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
     const uint64_t nbins = 1ull << nq;
     const uint64_t waves = nbins * M.nseg;
     k_marg_partial<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, M, scratch);
-    k_marg_final<<<blocks_for(nbins, kBlock), kBlock, 0, s>>>(scratch, nbins, M.nseg, out);
+    if (nbins < kBlock && M.nseg >= 64)
+        k_marg_final_block<<<(uint32_t)nbins, kBlock, 0, s>>>(scratch, nbins, M.nseg, out);
+    else
+        k_marg_final<<<blocks_for(nbins, kBlock), kBlock, 0, s>>>(scratch, nbins, M.nseg, out);
     return hipGetLastError();
 }
 
@@ -374,7 +419,7 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s
 {
     const uint64_t n16 = bytes / 16;
     uint32_t nb = blocks_for(n16, kBlock * 4);
-    if (nb > 65536) nb = 65536;
+    if (nb > 16384) nb = 16384;
     k_copy<<<nb, kBlock, 0, s>>>((uint4 *)dst, (const uint4 *)src, n16);
     return hipGetLastError();
 }

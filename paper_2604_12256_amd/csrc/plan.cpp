@@ -187,7 +187,7 @@ struct Builder {
                 if (reg_phys[b] == phys) return b;
             return -1;
         };
-        const int kTmax = 2;
+        const int kTmaxLane = 2, kTmaxUniform = 4;
         const uint32_t full = (1u << r) - 1;
         auto kernel_mask = [&](uint32_t S) { return popc(S) >= 3 ? full : S; };
         auto dense_cost = [&](uint32_t S) { return op_cost(false, popc(kernel_mask(S))); };
@@ -263,7 +263,9 @@ struct Builder {
                     if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
                 const bool diag2 = F.acc.diag && g.diag;
                 const double fused = diag2 ? op_cost(true, 0) : dense_cost(S2);
-                const bool sel_ok = (int)T2.size() <= kTmax && (diag2 || popc(kernel_mask(S2)) <= 2 || !lane_sel(T2));
+                const bool sel_ok = diag2 ? (int)T2.size() <= kTmaxUniform
+                                          : (lane_sel(T2) ? ((int)T2.size() <= kTmaxLane && popc(kernel_mask(S2)) <= 2)
+                                                          : (int)T2.size() <= kTmaxUniform);
                 if (sel_ok && fused <= F.indiv + gcost + 1e-9) {
                     std::vector<int> l2 = qlist(S2, T2);
                     if (l2 != F.acc.q) F.acc = embed(F.acc, l2);
@@ -275,7 +277,9 @@ struct Builder {
                 }
                 emit(F);
             }
-            const bool alone_ok = (int)gT.size() <= kTmax && (g.diag || popc(kernel_mask(gS)) <= 2 || !lane_sel(gT));
+            const bool alone_ok = g.diag ? (int)gT.size() <= kTmaxUniform
+                                         : (lane_sel(gT) ? ((int)gT.size() <= kTmaxLane && popc(kernel_mask(gS)) <= 2)
+                                                         : (int)gT.size() <= kTmaxUniform);
             if (!alone_ok) {
                 if (g.diag) {
                     push_diag(g.q, g.m);
@@ -344,12 +348,19 @@ struct Builder {
                 if ((R >> i) & 1) ph.reg.push_back(i);
             std::vector<int> reg_phys;
             for (int i : ph.reg) reg_phys.push_back(st.local[i]);
+            // thread-id bits: the non-register local bits least used by this
+            // phase's gates become lane bits, so that the bits selecting a
+            // fused block or indexing a diagonal table are wave-uniform
+            // whenever possible (scalar loads instead of per-lane loads)
+            std::vector<int> uses(C, 0);
+            for (int gi : take)
+                for (int q : all[gi].q)
+                    if (local_of[q] >= 0 && !((R >> local_of[q]) & 1)) uses[local_of[q]]++;
+            for (int i = 0; i < C; ++i)
+                if (!((R >> i) & 1)) ph.tmap.push_back(i);
+            std::stable_sort(ph.tmap.begin(), ph.tmap.end(), [&](int a, int b) { return uses[a] < uses[b]; });
             uint64_t lane_phys = 0;
-            for (int i = 0, cnt = 0; i < C && cnt < 6; ++i)
-                if (!((R >> i) & 1)) {
-                    lane_phys |= 1ull << st.local[i];
-                    ++cnt;
-                }
+            for (int i = 0; i < 6 && i < (int)ph.tmap.size(); ++i) lane_phys |= 1ull << st.local[ph.tmap[i]];
             std::vector<const Operator *> tg;
             for (int gi : take) {
                 tg.push_back(&all[gi]);
@@ -501,14 +512,55 @@ struct Builder {
         }
     }
 
-    // Executes the gates of one buffer with the enabled passes.
+    // Estimated device time of an op (cost model of the adaptive simulator):
+    // the larger of its HBM time and its arithmetic time at sustained rates,
+    // plus a launch overhead.
+    static double est_seconds(const PlanOp &op)
+    {
+        return std::max(op.bytes / 5.5e12, op.flops / 55e12) + 4e-6;
+    }
+
+    // Executes the gates of one buffer with the enabled passes.  With cache
+    // blocking on, the diagonal detector's fused tables may block more stage
+    // boundaries than they save (diagonals fuse into neighbouring dense blocks
+    // for free inside a stage), so both lowerings are built and the cheaper
+    // one by the cost model is kept.
     void lower(int buffer, int nb, std::vector<Operator> gates)
     {
+        if ((o.opt & SIM_OPT_DIAG) && (o.opt & SIM_OPT_STAGES)) {
+            const size_t mark = plan.ops.size();
+            const PlanStats saved = plan.stats;
+            uint64_t v = 0;
+            std::vector<Operator> dd = diagonal_detector(nb, (int)o.D, gates, &v);
+            lower_gates(buffer, nb, std::move(dd));
+            double t_dd = 0;
+            for (size_t i = mark; i < plan.ops.size(); ++i) t_dd += est_seconds(plan.ops[i]);
+            std::vector<PlanOp> with_dd(std::make_move_iterator(plan.ops.begin() + mark),
+                                        std::make_move_iterator(plan.ops.end()));
+            plan.ops.resize(mark);
+            const PlanStats stats_dd = plan.stats;
+            plan.stats = saved;
+            lower_gates(buffer, nb, gates);
+            double t_plain = 0;
+            for (size_t i = mark; i < plan.ops.size(); ++i) t_plain += est_seconds(plan.ops[i]);
+            if (t_dd < t_plain) {
+                plan.ops.resize(mark);
+                for (PlanOp &op : with_dd) plan.ops.push_back(std::move(op));
+                plan.stats = stats_dd;
+            }
+            plan.stats.dd_visits += v;
+            return;
+        }
         if (o.opt & SIM_OPT_DIAG) {
             uint64_t v = 0;
             gates = diagonal_detector(nb, (int)o.D, gates, &v);
             plan.stats.dd_visits += v;
         }
+        lower_gates(buffer, nb, std::move(gates));
+    }
+
+    void lower_gates(int buffer, int nb, std::vector<Operator> gates)
+    {
         if (gates.empty()) return;
         const bool small = buffer != 0 && nb <= (plan.dtype == SIM_C128 ? 13 : 14);
         if ((o.opt & SIM_OPT_STAGES) && small) {

@@ -114,6 +114,7 @@ def load_library() -> ctypes.CDLL:
         "sim_plan_counters": (I, [P, P, P, P]),
         "sim_plan_destroy": (I, [P]),
         "sim_version": (ctypes.c_char_p, []),
+        "sim_device_copy": (I, [P, P, U64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -247,6 +248,17 @@ class Simulator:
             self.close()
         except Exception:
             pass
+
+
+def device_copy(dst, src, stream=None) -> None:
+    """Plain device copy between two torch tensors (bandwidth reference)."""
+    import torch
+    lib = load_library()
+    nbytes = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
+    s = stream if stream is not None else torch.cuda.current_stream(dst.device)
+    st = lib.sim_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    if st != OK:
+        raise QsimError(st, "sim_device_copy failed")
 
 
 def run_batch(sims: Sequence[Simulator], stream=None) -> None:

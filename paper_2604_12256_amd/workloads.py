@@ -176,6 +176,11 @@ def random_mixed(n: int, n_gates: int, seed: int, max_k: int = 3,
     return gates
 
 
+def layered_gate_count(n: int, layers: int) -> int:
+    """Number of gates of layered(n, layers, seed)."""
+    return layers * (n + n // 4 + n)
+
+
 @dataclass
 class Request:
     rid: int

@@ -97,12 +97,14 @@ def test_complex64_paths(oracle_mod):
             check64(got, want, oracle_mod, f"c64 n={n} opt={opt}")
 
 
-def test_forced_five_qubit_fusion(oracle_mod):
+@pytest.mark.parametrize("k", [4, 5])
+def test_forced_fusion_mfma(oracle_mod, k):
+    """Fused 4- and 5-qubit gates run as batched GEMMs on the matrix cores."""
     n, gates = 16, W.layered(16, 6, 11)
     want = oracle_mod.run(n, gates)
     for dtype in ("c128", "c64"):
-        say(f"fuse5 {dtype}")
-        got, st = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_FUSE, force_fuse_k=5)
+        say(f"fuse{k} {dtype}")
+        got, st = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_FUSE, force_fuse_k=k)
         if dtype == "c128":
             check128(got, want, "fuse5")
         else:
@@ -261,3 +263,39 @@ def test_complex64_32q_against_complex128():
     assert abs(a.norm() - 1) < 1e-11
     a.close()
     b.close()
+
+
+def test_batched_small_circuits(oracle_mod):
+    """One launch for many small circuits (serving path): each result equals
+    the oracle and its solo run."""
+    import torch
+    sims, wants = [], []
+    for i in range(20):
+        n = 4 + (i % 10)
+        gates = W.layered(n, 3 + i % 5, seed=100 + i)
+        sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+        sim.load(gates)
+        sims.append(sim)
+        wants.append(oracle_mod.run(n, gates))
+    qsim.run_batch(sims)
+    torch.cuda.synchronize()
+    for sim, want in zip(sims, wants):
+        got = sim.amplitudes()
+        check128(got, want, f"batch n={sim.n}")
+        sim.run()
+        solo = sim.amplitudes()
+        check128(solo, got, "solo vs batch")
+        sim.close()
+    # complex64 batch
+    sims = []
+    for i in range(6):
+        n = 10 + i % 5
+        sim = qsim.Simulator(n, dtype="c64", opt=qsim.OPT_ALL)
+        gates = W.layered(n, 4, seed=200 + i)
+        sim.load(gates)
+        sims.append((sim, oracle_mod.run(n, gates)))
+    qsim.run_batch([s for s, _ in sims])
+    torch.cuda.synchronize()
+    for sim, want in sims:
+        check64(sim.amplitudes(), want, oracle_mod, "batch c64")
+        sim.close()

@@ -183,20 +183,50 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
                     if ((lane_phys >> t) & 1) uni = false;
                 op[3] = uni ? 1u : 0u;
             } else {
+                // diagonal: register bits of the index -> mask, the other bits
+                // select a block of 2^|mask| factors (table [sel][register part])
+                uint32_t mask = 0;
+                std::vector<int> sel;
+                std::vector<int> regbit_of(k.dq.size(), -1), selbit_of(k.dq.size(), -1);
+                for (size_t t = 0; t < k.dq.size(); ++t) {
+                    int b = -1;
+                    for (int u = 0; u < reg_bits; ++u)
+                        if (reg_phys[u] == k.dq[t]) b = u;
+                    if (b >= 0) {
+                        mask |= 1u << b;
+                        regbit_of[t] = b;
+                    } else {
+                        selbit_of[t] = (int)sel.size();
+                        sel.push_back(k.dq[t]);
+                    }
+                }
+                if (sel.size() > 32) throw std::runtime_error("encode_stage: diagonal too wide");
+                const int km = __builtin_popcount(mask);
+                std::vector<int> rank(reg_bits, -1);  // register bit -> bit of the register part
+                for (int u = 0, r = 0; u < reg_bits; ++u)
+                    if ((mask >> u) & 1) rank[u] = r++;
+                std::vector<cplx> tab((size_t)1 << (sel.size() + km));
+                for (uint64_t sv = 0; sv < (1ull << sel.size()); ++sv)
+                    for (uint64_t jm = 0; jm < (1ull << km); ++jm) {
+                        uint64_t y = 0;
+                        for (size_t t = 0; t < k.dq.size(); ++t) {
+                            const uint64_t bit = regbit_of[t] >= 0 ? (jm >> rank[regbit_of[t]]) & 1
+                                                                   : (sv >> selbit_of[t]) & 1;
+                            y |= bit << t;
+                        }
+                        tab[(sv << km) | jm] = k.table[y];
+                    }
+                tables.resize(toff);  // replace the semantic table by the kernel layout
+                tables.insert(tables.end(), tab.begin(), tab.end());
+                for (int t = 8; t < 16; ++t) op[t] = 0;
+                for (size_t t = 0; t < sel.size(); ++t) op[8 + t / 4] |= (uint32_t)sel[t] << (8 * (t % 4));
                 op[0] = 2;
-                op[1] = (uint32_t)k.dq.size();
+                op[1] = mask;
+                op[2] = (uint32_t)sel.size();
                 bool uni = true;
-                for (int t : k.dq)
+                for (int t : sel)
                     if ((lane_phys >> t) & 1) uni = false;
                 op[3] = uni ? 1u : 0u;
-                if (k.dq.size() > 24) throw std::runtime_error("encode_stage: diagonal too wide");
-                for (int j = 0; j < (1 << reg_bits); ++j) {
-                    uint32_t y = 0;
-                    for (size_t t = 0; t < k.dq.size(); ++t)
-                        for (int b = 0; b < reg_bits; ++b)
-                            if (k.dq[t] == reg_phys[b] && ((j >> b) & 1)) y |= 1u << t;
-                    op[16 + j / 2] |= y << (16 * (j & 1));
-                }
             }
         }
     }

@@ -9,8 +9,10 @@
 // 16x16x4 MFMA steps: complex64 states on FP32 MFMA, complex128 on FP64 MFMA.
 //
 // Operand layout of the 16x16x4 MFMA (one block): lane l = j + 16 q holds
-// A[j][q] and B[q][j] of each k-step, and D[4q + v][j] in accumulator v.
-// Every lane keeps its slice of M_r in registers for the whole launch.
+// A[j][q] and B[q][j] of each k-step.  Accumulator v of lane l holds
+// D[4q + v][j] for the FP32 instruction and D[4v + q][j] for the FP64 one
+// (output groups of 4 rows vs 1 row per lane block).  Every lane keeps its
+// slice of M_r in registers for the whole launch.
 #include "device.hpp"
 
 namespace qs {
@@ -21,6 +23,7 @@ constexpr int kMfmaThreads = 256;
 
 template <typename R> struct Mfma;
 template <> struct Mfma<float> {
+    static constexpr bool kRowsPerLaneContiguous = true;   // D[4q + v][j]
     typedef float acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
     {
@@ -28,6 +31,7 @@ template <> struct Mfma<float> {
     }
 };
 template <> struct Mfma<double> {
+    static constexpr bool kRowsPerLaneContiguous = false;  // D[4v + q][j]
     typedef double acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
     {
@@ -63,11 +67,22 @@ __global__ __launch_bounds__(kMfmaThreads) void k_dense_mfma(c2_t<R> *__restrict
     uint64_t in_off[S];   // B row 4s + q -> amplitude 2s + q/2, part q%2
 #pragma unroll
     for (int s = 0; s < S; ++s) in_off[s] = off(2 * s + (int)(q >> 1));
-    uint64_t out_off[T][2];  // D rows 16t + 4q + v -> amplitudes 8t + 2q + v/2
+    // Output amplitudes written by this lane, two per tile:
+    //  rows 16t + 4q + v (FP32): amplitudes 8t + 2q + {0, 1}, (re, im) = (v0, v1), (v2, v3);
+    //  rows 16t + 4v + q (FP64): lane holds re (q even) or im (q odd) of amplitudes
+    //  8t + 2v + q/2; the partner lane l ^ 16 holds the other part, so even-q lanes
+    //  write v = 0, 1 and odd-q lanes v = 2, 3.
+    uint64_t out_off[T][2];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        out_off[t][0] = off(8 * t + 2 * (int)q);
-        out_off[t][1] = off(8 * t + 2 * (int)q + 1);
+        if (Mfma<R>::kRowsPerLaneContiguous) {
+            out_off[t][0] = off(8 * t + 2 * (int)q);
+            out_off[t][1] = off(8 * t + 2 * (int)q + 1);
+        } else {
+            const int v0 = (q & 1) ? 2 : 0;
+            out_off[t][0] = off(8 * t + 2 * v0 + (int)(q >> 1));
+            out_off[t][1] = off(8 * t + 2 * (v0 + 1) + (int)(q >> 1));
+        }
     }
 
     const uint64_t wave = ((uint64_t)blockIdx.x * kMfmaThreads + threadIdx.x) >> 6;
@@ -90,10 +105,30 @@ __global__ __launch_bounds__(kMfmaThreads) void k_dense_mfma(c2_t<R> *__restrict
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             V y0, y1;
-            y0.x = acc[t][0];
-            y0.y = acc[t][1];
-            y1.x = acc[t][2];
-            y1.y = acc[t][3];
+            if (Mfma<R>::kRowsPerLaneContiguous) {
+                y0.x = acc[t][0];
+                y0.y = acc[t][1];
+                y1.x = acc[t][2];
+                y1.y = acc[t][3];
+            } else {
+                R mine[4], other[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    mine[v] = acc[t][v];
+                    other[v] = __shfl_xor(mine[v], 16, 64);
+                }
+                if ((q & 1) == 0) {  // own = re, partner = im; amplitudes of v = 0, 1
+                    y0.x = mine[0];
+                    y0.y = other[0];
+                    y1.x = mine[1];
+                    y1.y = other[1];
+                } else {             // own = im, partner = re; amplitudes of v = 2, 3
+                    y0.x = other[2];
+                    y0.y = mine[2];
+                    y1.x = other[3];
+                    y1.y = mine[3];
+                }
+            }
             a[base | out_off[t][0]] = y0;
             a[base | out_off[t][1]] = y1;
         }

@@ -21,9 +21,11 @@
 //   phase   [0] nops  [1] non-register local mask  [2] register local mask
 //           [4..7] local bit of thread-id bit i (bytes; bits 0..5 are the lane bits)
 //           [16 + 32 o ...] op o
-//   op      [0] type (1 dense, 2 diagonal)  [1] register mask | diagonal size
-//           [2] selector count  [3] selector / table index wave-uniform  [4,5] table offset
-//           [8..15] bit positions (bytes)  [16..31] diagonal: register index part (u16)
+//   op      [0] type (1 dense, 2 diagonal)  [1] register mask (bits of the register
+//           tile the operator acts on)  [2] selector count  [3] selectors wave-uniform
+//           [4,5] table offset  [8..15] physical selector bit positions (bytes)
+//   A dense op's table holds 2^nsel matrices of (2^k)^2 entries, a diagonal
+//   op's 2^nsel blocks of 2^k factors (k = popcount of the register mask).
 #include "device.hpp"
 
 namespace qs {
@@ -104,6 +106,34 @@ __device__ __forceinline__ void apply_dense(c2_t<R> *amp, MP m)
             for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
             amp[idx[r]] = acc;
         }
+    }
+}
+
+// Diagonal operator on the register bits of MASK: register j is multiplied by
+// t[bits of j under MASK].
+template <typename R, int RB, int MASK, typename MP>
+__device__ __forceinline__ void apply_diag(c2_t<R> *amp, MP t)
+{
+    constexpr int NR = 1 << RB;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        int idx = 0, bit = 0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if ((MASK >> b) & 1) {
+                if ((j >> b) & 1) idx |= 1 << bit;
+                ++bit;
+            }
+        amp[j] = cmul(amp[j], ldc<R>(t, (uint64_t)idx));
+    }
+}
+
+template <typename R, int RB, int M = 0, typename MP>
+__device__ __forceinline__ void dispatch_diag(uint32_t mask, c2_t<R> *amp, MP t)
+{
+    if constexpr (M < (1 << RB)) {
+        if (mask == (uint32_t)M) apply_diag<R, RB, M, MP>(amp, t);
+        else dispatch_diag<R, RB, M + 1, MP>(mask, amp, t);
     }
 }
 
@@ -226,33 +256,31 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
             }
             const uint32_t lb = cur_lb;
             const uint64_t phys_base = cbase | deposit(lb, Lmask);
+            // wave-uniform bits (wave part of the thread id and the chunk bits)
+            // taken from the first lane, for scalar selector extraction
+            const uint64_t pb_u = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(phys_base >> 32)) << 32) |
+                                  (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)phys_base);
             for (uint32_t o = 0; o < nops; ++o) {
                 const QS_CONST uint32_t *op = ph + 16 + 32 * o;
                 const uint64_t toff = (uint64_t)op[4] | ((uint64_t)op[5] << 32);
-                if (op[0] == 1u) {
-                    const uint32_t mask = op[1], nsel = op[2];
+                const uint32_t mask = op[1], nsel = op[2];
+                const int k = __builtin_popcount(mask);
+                if (op[3]) {  // selectors constant across the wave: scalar extraction, scalar loads
+                    uint32_t sel = 0;
+                    for (uint32_t u = 0; u < nsel; ++u)
+                        sel |= (uint32_t)((pb_u >> byte_at(op + 8, (int)u)) & 1ull) << u;
+                    if (op[0] == 1u)
+                        dispatch_dense<R, RB>(mask, amp, ctables + 2 * (toff + ((uint64_t)sel << (2 * k))));
+                    else
+                        dispatch_diag<R, RB>(mask, amp, ctables + 2 * (toff + ((uint64_t)sel << k)));
+                } else {      // selectors vary by lane: per-lane loads
                     uint32_t sel = 0;
                     for (uint32_t u = 0; u < nsel; ++u)
                         sel |= (uint32_t)((phys_base >> byte_at(op + 8, (int)u)) & 1ull) << u;
-                    const int k = __builtin_popcount(mask);
-                    const uint32_t msz = 1u << (2 * k);
-                    if (op[3]) {  // block selector constant across the wave: scalar loads
-                        sel = __builtin_amdgcn_readfirstlane(sel);
-                        dispatch_dense<R, RB>(mask, amp, ctables + 2 * (toff + (uint64_t)sel * msz));
-                    } else {      // selector varies by lane: per-lane loads
-                        dispatch_dense<R, RB>(mask, amp, rtables + 2 * (toff + (uint64_t)sel * msz));
-                    }
-                } else {
-                    const uint32_t nd = op[1];
-                    uint32_t yc = 0;
-                    for (uint32_t t = 0; t < nd; ++t)
-                        yc |= (uint32_t)((phys_base >> byte_at(op + 8, (int)t)) & 1ull) << t;
-                    const V *T = tables + toff;
-#pragma unroll
-                    for (int j = 0; j < NR; ++j) {
-                        const uint32_t yr = (op[16 + (j >> 1)] >> ((j & 1) * 16)) & 0xffffu;
-                        amp[j] = cmul(amp[j], T[yc | yr]);
-                    }
+                    if (op[0] == 1u)
+                        dispatch_dense<R, RB>(mask, amp, rtables + 2 * (toff + ((uint64_t)sel << (2 * k))));
+                    else
+                        dispatch_diag<R, RB>(mask, amp, rtables + 2 * (toff + ((uint64_t)sel << k)));
                 }
             }
         }

@@ -19,8 +19,17 @@ namespace {
 
 int popc(uint64_t x) { return __builtin_popcountll(x); }
 
-// FMA per amplitude of one operator applied to registers (cost model).
-double op_cost(bool diag, int dense_qubits) { return diag ? 4.0 : 4.0 * double(1 << dense_qubits); }
+// Cost model of one stage-kernel operator, in FMA-equivalents per amplitude
+// divided by the fraction of FP64 peak the operator reaches on MI355X
+// (measured per operator type at 30 qubits: a dense operator on 1 register
+// bit ~0.5, on 2 bits ~0.6, on the full 4-bit register tile ~0.28; a
+// diagonal one complex multiply per amplitude).
+double op_cost(bool diag, int dense_qubits)
+{
+    if (diag) return 4.0 / 0.5;
+    static const double eff[] = {1.0, 0.5, 0.6, 0.4, 0.28, 0.3};
+    return 4.0 * double(1 << dense_qubits) / eff[dense_qubits < 5 ? dense_qubits : 5];
+}
 // Floating-point operations per amplitude: a dense k-qubit operator does 2^k
 // complex multiply-adds (8 flops each), a diagonal one complex multiply (6).
 double op_flops(bool diag, int dense_qubits) { return diag ? 6.0 : 8.0 * double(1 << dense_qubits); }
@@ -188,6 +197,7 @@ struct Builder {
             return -1;
         };
         const int kTmaxLane = 2, kTmaxUniform = 4;
+        const bool fuse = (o.opt & SIM_OPT_FUSE) != 0;  // without it every gate is its own kernel op
         const uint32_t full = (1u << r) - 1;
         auto kernel_mask = [&](uint32_t S) { return popc(S) >= 3 ? full : S; };
         auto dense_cost = [&](uint32_t S) { return op_cost(false, popc(kernel_mask(S))); };
@@ -266,7 +276,7 @@ struct Builder {
                 const bool sel_ok = diag2 ? (int)T2.size() <= kTmaxUniform
                                           : (lane_sel(T2) ? ((int)T2.size() <= kTmaxLane && popc(kernel_mask(S2)) <= 2)
                                                           : (int)T2.size() <= kTmaxUniform);
-                if (sel_ok && fused <= F.indiv + gcost + 1e-9) {
+                if (fuse && sel_ok && fused <= F.indiv + gcost + 1e-9) {
                     std::vector<int> l2 = qlist(S2, T2);
                     if (l2 != F.acc.q) F.acc = embed(F.acc, l2);
                     apply_left(F.acc, g);

@@ -79,7 +79,8 @@ enum {
     SIM_OPT_FUSE = 1u << 1,    /* cost-based gate fusion up to F qubits */
     SIM_OPT_STAGES = 1u << 2,  /* cache blocking: chunk-resident stages (Alg. 2, Alg. 5) */
     SIM_OPT_BOOST = 1u << 3,   /* merge booster (Sec. 4.4, Alg. 6-7) */
-    SIM_OPT_ALL = 0xFu
+    SIM_OPT_REMAP = 1u << 4,   /* qubit reordering between stages (Sec. 2.3), needs STAGES */
+    SIM_OPT_ALL = 0x1Fu
 };
 
 typedef struct {

@@ -25,6 +25,8 @@ struct Prepared {
     int buffer = 0, nb = 0;
     qs::GateDesc gd{};          // DENSE / DIAG
     int lo = 0, hi = 0;         // KRON sources
+    int npairs = 0;             // PERM: exchanged physical bit pairs
+    int plo[6] = {0}, phi[6] = {0};
     size_t prog_off = 0;        // STAGE: word offset of its program
     int C = 0, nph = 0;
     uint64_t nchunks = 0;
@@ -151,7 +153,7 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
         const qs::Phase &ph = st.phases[p];
         w[base + 32 + p] = (uint32_t)(w.size() - base);
         const size_t pb = w.size();
-        w.resize(pb + 16 + 32 * ph.ops.size(), 0);
+        w.resize(pb + 16 + 16 * ph.ops.size(), 0);
         uint32_t rmask = 0;
         for (int i : ph.reg) rmask |= 1u << i;
         const uint32_t nonr = ((1u << C) - 1) & ~rmask;
@@ -166,27 +168,17 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
         for (int i = 0; i < 6; ++i) lane_phys |= 1ull << st.local[ph.tmap[i]];
         for (size_t o = 0; o < ph.ops.size(); ++o) {
             const qs::KOp &k = ph.ops[o];
-            uint32_t *op = &w[pb + 16 + 32 * o];
+            uint32_t *op = &w[pb + 16 + 16 * o];
             const uint64_t toff = tables.size();
-            tables.insert(tables.end(), k.table.begin(), k.table.end());
-            op[4] = (uint32_t)toff;
-            op[5] = (uint32_t)(toff >> 32);
-            const std::vector<int> &pos = k.type == qs::KOp::DENSE ? k.sel : k.dq;
-            if (pos.size() > 32) throw std::runtime_error("encode_stage: too many bit positions");
-            for (size_t t = 0; t < pos.size(); ++t) op[8 + t / 4] |= (uint32_t)pos[t] << (8 * (t % 4));
+            uint32_t mask = 0;
+            std::vector<int> sel;
             if (k.type == qs::KOp::DENSE) {
-                op[0] = 1;
-                op[1] = k.reg_mask;
-                op[2] = (uint32_t)k.sel.size();
-                bool uni = true;
-                for (int t : k.sel)
-                    if ((lane_phys >> t) & 1) uni = false;
-                op[3] = uni ? 1u : 0u;
+                mask = k.reg_mask;
+                sel = k.sel;
+                tables.insert(tables.end(), k.table.begin(), k.table.end());
             } else {
                 // diagonal: register bits of the index -> mask, the other bits
                 // select a block of 2^|mask| factors (table [sel][register part])
-                uint32_t mask = 0;
-                std::vector<int> sel;
                 std::vector<int> regbit_of(k.dq.size(), -1), selbit_of(k.dq.size(), -1);
                 for (size_t t = 0; t < k.dq.size(); ++t) {
                     int b = -1;
@@ -200,11 +192,11 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
                         sel.push_back(k.dq[t]);
                     }
                 }
-                if (sel.size() > 32) throw std::runtime_error("encode_stage: diagonal too wide");
                 const int km = __builtin_popcount(mask);
                 std::vector<int> rank(reg_bits, -1);  // register bit -> bit of the register part
                 for (int u = 0, r = 0; u < reg_bits; ++u)
                     if ((mask >> u) & 1) rank[u] = r++;
+                if (sel.size() > 24) throw std::runtime_error("encode_stage: diagonal too wide");
                 std::vector<cplx> tab((size_t)1 << (sel.size() + km));
                 for (uint64_t sv = 0; sv < (1ull << sel.size()); ++sv)
                     for (uint64_t jm = 0; jm < (1ull << km); ++jm) {
@@ -216,18 +208,17 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
                         }
                         tab[(sv << km) | jm] = k.table[y];
                     }
-                tables.resize(toff);  // replace the semantic table by the kernel layout
                 tables.insert(tables.end(), tab.begin(), tab.end());
-                for (int t = 8; t < 16; ++t) op[t] = 0;
-                for (size_t t = 0; t < sel.size(); ++t) op[8 + t / 4] |= (uint32_t)sel[t] << (8 * (t % 4));
-                op[0] = 2;
-                op[1] = mask;
-                op[2] = (uint32_t)sel.size();
-                bool uni = true;
-                for (int t : sel)
-                    if ((lane_phys >> t) & 1) uni = false;
-                op[3] = uni ? 1u : 0u;
             }
+            if (sel.size() > 32) throw std::runtime_error("encode_stage: too many selector bits");
+            bool uni = true;
+            for (int t : sel)
+                if ((lane_phys >> t) & 1) uni = false;
+            op[0] = (k.type == qs::KOp::DENSE ? 1u : 2u) | (mask << 8) | ((uint32_t)sel.size() << 16) |
+                    ((uni ? 1u : 0u) << 24);
+            op[1] = (uint32_t)toff;
+            op[2] = (uint32_t)(toff >> 32);
+            for (size_t t = 0; t < sel.size(); ++t) op[3 + t / 4] |= (uint32_t)sel[t] << (8 * (t % 4));
         }
     }
 }
@@ -310,6 +301,24 @@ sim_status prepare(sim_ctx *c)
                 tables.insert(tables.end(), op.op.m.begin(), op.op.m.end());
             }
             p.gd = desc_of(op.op, toff);
+            break;
+        }
+        case SIM_OP_PERM: {
+            // a product of exchanges of low bits (< 6) with high bits
+            const int low = std::min(6, op.buffer_qubits);
+            for (int q = 0; q < op.buffer_qubits; ++q) {
+                const int d = op.perm[q];
+                if (d == q) continue;
+                if (op.perm[d] != q) return fail(c, SIM_E_UNSUPPORTED, "permutation is not a product of swaps");
+                if (q < low) {
+                    if (d < low || p.npairs >= 6) return fail(c, SIM_E_UNSUPPORTED, "unsupported permutation");
+                    p.plo[p.npairs] = q;
+                    p.phi[p.npairs] = d;
+                    ++p.npairs;
+                } else if (d >= low) {
+                    return fail(c, SIM_E_UNSUPPORTED, "unsupported permutation");
+                }
+            }
             break;
         }
         case SIM_OP_STAGE: {
@@ -440,6 +449,9 @@ sim_status execute(sim_ctx *c)
             else
                 e = qs::launch_dense<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp,
                                         c->stream);
+            break;
+        case SIM_OP_PERM:
+            e = qs::launch_swap_bits<R>(c->buf(p.buffer), p.nb, p.plo, p.phi, p.npairs, c->stream);
             break;
         case SIM_OP_DIAG:
             e = qs::launch_diag_q<R>(c->buf(p.buffer), p.nb, (int)p.gd.k, p.gd.q,
@@ -690,8 +702,30 @@ sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out)
     if (!out) return fail(a, SIM_E_INVAL, "out is NULL");
     if (a->n != b->n) return fail(a, SIM_E_INVAL, "qubit counts differ");
     if (!a->ran || !b->ran) return fail(a, SIM_E_STATE, "both contexts must have run");
-    if (a->plan.layout != b->plan.layout) return fail(a, SIM_E_UNSUPPORTED, "states use different qubit layouts");
     HIPCHK(a, hipStreamSynchronize(b->stream), "synchronize");
+    if (a->plan.layout != b->plan.layout) {
+        // element i of a (physical) is logical x = pa^-1(i); b holds it at pb(x)
+        std::vector<int> inv_a(a->n), map(a->n);
+        for (int q = 0; q < a->n; ++q) inv_a[a->plan.layout[q]] = q;
+        for (int p = 0; p < a->n; ++p) map[p] = b->plan.layout[inv_a[p]];
+        const size_t scr = qs::inner_scratch_bytes(a->n);
+        HIPCHK(a, grow(a->scratch, scr + 64), "scratch allocation");
+        double *dout = (double *)((char *)a->scratch.p + scr);
+        hipError_t e;
+        double *sp = (double *)a->scratch.p;
+        if (a->dtype == SIM_C128 && b->dtype == SIM_C128)
+            e = qs::launch_inner_perm<double, double>(a->state, b->state, a->n, map.data(), dout, sp, a->stream);
+        else if (a->dtype == SIM_C128)
+            e = qs::launch_inner_perm<double, float>(a->state, b->state, a->n, map.data(), dout, sp, a->stream);
+        else if (b->dtype == SIM_C128)
+            e = qs::launch_inner_perm<float, double>(a->state, b->state, a->n, map.data(), dout, sp, a->stream);
+        else
+            e = qs::launch_inner_perm<float, float>(a->state, b->state, a->n, map.data(), dout, sp, a->stream);
+        if (e != hipSuccess) return hip_fail(a, e, "inner product");
+        HIPCHK(a, hipMemcpyAsync(out, dout, 16, hipMemcpyDeviceToHost, a->stream), "copy out");
+        HIPCHK(a, hipStreamSynchronize(a->stream), "synchronize");
+        return SIM_OK;
+    }
     const size_t scr = qs::inner_scratch_bytes(a->n);
     HIPCHK(a, grow(a->scratch, scr + 64), "scratch allocation");
     double *dout = (double *)((char *)a->scratch.p + scr);

@@ -106,6 +106,11 @@ template <typename R> hipError_t launch_dense_mfma(void *state, int n, const Gat
 template <typename R> hipError_t launch_diag_q(void *state, int n, int k, const int *q, const void *table, hipStream_t s);
 template <typename R> hipError_t launch_kron(void *dst, const void *lo, int nlo, const void *hi, int nhi, hipStream_t s);
 template <typename R> hipError_t launch_perm(void *dst, const void *src, int n, const int *perm, hipStream_t s);
+// in-place exchange of physical bits lo[k] <-> hi[k] (lo < 6 <= hi)
+template <typename R> hipError_t launch_swap_bits(void *state, int n, const int *lo, const int *hi, int npairs,
+                                                  hipStream_t s);
+template <typename RA, typename RB> hipError_t launch_inner_perm(const void *a, const void *b, int n, const int *map,
+                                                                 double *out, double *scratch, hipStream_t s);
 template <typename R> hipError_t launch_gather(const void *state, const uint64_t *idx, uint64_t m, double *out, hipStream_t s);
 // marginal over the physical qubits q[0..nq): out[2^nq] doubles (device), scratch as sized by marginal_scratch_bytes
 template <typename R> hipError_t launch_marginal(const void *state, int n, const int *q, int nq, double *out,

@@ -20,10 +20,11 @@
 //           [8 + i] physical bit of local bit i (i < C)   [32 + p] word offset of phase p
 //   phase   [0] nops  [1] non-register local mask  [2] register local mask
 //           [4..7] local bit of thread-id bit i (bytes; bits 0..5 are the lane bits)
-//           [16 + 32 o ...] op o
-//   op      [0] type (1 dense, 2 diagonal)  [1] register mask (bits of the register
-//           tile the operator acts on)  [2] selector count  [3] selectors wave-uniform
-//           [4,5] table offset  [8..15] physical selector bit positions (bytes)
+//           [16 + 16 o ...] op o (a 64-byte record, loaded in one scalar load)
+//   op      [0] type (bits 0-7: 1 dense, 2 diagonal) | register mask (bits of the
+//           register tile the operator acts on) << 8 | selector count << 16 |
+//           selectors wave-uniform << 24   [1,2] table offset
+//           [3..10] physical selector bit positions (bytes)
 //   A dense op's table holds 2^nsel matrices of (2^k)^2 entries, a diagonal
 //   op's 2^nsel blocks of 2^k factors (k = popcount of the register mask).
 #include "device.hpp"
@@ -50,6 +51,38 @@ template <> __device__ __forceinline__ uint32_t swz<float>(uint32_t i)
 __device__ __forceinline__ uint32_t byte_at(const QS_CONST uint32_t *w, int i)
 {
     return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+}
+
+struct __attribute__((aligned(64))) OpRec {
+    uint32_t w[16];
+};
+
+__device__ __forceinline__ OpRec load_rec(const QS_CONST uint32_t *p)
+{
+    OpRec r;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r.w[i] = p[i];
+    return r;
+}
+
+// Bits of `bits` at the selector positions of an op record (bit u of the
+// result = bit pos[u]).  Up to four selectors come from the record held in
+// scalar registers; wider diagonals read their positions from memory.
+template <typename B>
+__device__ __forceinline__ uint32_t gather_sel(const OpRec &r, const QS_CONST uint32_t *rec, uint32_t nsel, B bits)
+{
+    uint32_t sel = 0;
+    if (nsel <= 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t pos = (r.w[3] >> (8 * u)) & 0xffu;
+            if ((uint32_t)u < nsel) sel |= (uint32_t)((bits >> pos) & 1ull) << u;
+        }
+    } else {
+        for (uint32_t u = 0; u < nsel; ++u)
+            sel |= (uint32_t)((bits >> byte_at(rec + 3, (int)u)) & 1ull) << u;
+    }
+    return sel;
 }
 
 template <int RB>
@@ -260,28 +293,29 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
             // taken from the first lane, for scalar selector extraction
             const uint64_t pb_u = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(phys_base >> 32)) << 32) |
                                   (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)phys_base);
+            const QS_CONST uint32_t *recs = ph + 16;
+            OpRec cur = load_rec(recs);
             for (uint32_t o = 0; o < nops; ++o) {
-                const QS_CONST uint32_t *op = ph + 16 + 32 * o;
-                const uint64_t toff = (uint64_t)op[4] | ((uint64_t)op[5] << 32);
-                const uint32_t mask = op[1], nsel = op[2];
+                OpRec nxt;
+                if (o + 1 < nops) nxt = load_rec(recs + 16 * (o + 1));  // prefetch the next record
+                const uint32_t head = cur.w[0];
+                const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0xffu;
+                const uint64_t toff = (uint64_t)cur.w[1] | ((uint64_t)cur.w[2] << 32);
                 const int k = __builtin_popcount(mask);
-                if (op[3]) {  // selectors constant across the wave: scalar extraction, scalar loads
-                    uint32_t sel = 0;
-                    for (uint32_t u = 0; u < nsel; ++u)
-                        sel |= (uint32_t)((pb_u >> byte_at(op + 8, (int)u)) & 1ull) << u;
-                    if (op[0] == 1u)
+                if ((head >> 24) & 1u) {  // selectors constant across the wave: scalar extraction and loads
+                    const uint32_t sel = gather_sel(cur, recs + 16 * o, nsel, pb_u);
+                    if ((head & 0xffu) == 1u)
                         dispatch_dense<R, RB>(mask, amp, ctables + 2 * (toff + ((uint64_t)sel << (2 * k))));
                     else
                         dispatch_diag<R, RB>(mask, amp, ctables + 2 * (toff + ((uint64_t)sel << k)));
-                } else {      // selectors vary by lane: per-lane loads
-                    uint32_t sel = 0;
-                    for (uint32_t u = 0; u < nsel; ++u)
-                        sel |= (uint32_t)((phys_base >> byte_at(op + 8, (int)u)) & 1ull) << u;
-                    if (op[0] == 1u)
+                } else {                  // selectors vary by lane: per-lane loads
+                    const uint32_t sel = gather_sel(cur, recs + 16 * o, nsel, phys_base);
+                    if ((head & 0xffu) == 1u)
                         dispatch_dense<R, RB>(mask, amp, rtables + 2 * (toff + ((uint64_t)sel << (2 * k))));
                     else
                         dispatch_diag<R, RB>(mask, amp, rtables + 2 * (toff + ((uint64_t)sel << k)));
                 }
+                cur = nxt;
             }
         }
         if (cur_r != neutral_r || cur_t0 != neutral_t[0] || cur_t1 != neutral_t[1] || cur_t2 != neutral_t[2])

@@ -126,6 +126,80 @@ __global__ __launch_bounds__(kBlock) void k_perm(c2_t<R> *__restrict__ dst, cons
     dst[y] = src[x];
 }
 
+// Qubit reordering in place (Sec. 2.3, Eq. of the swap gate): exchanges
+// physical bits lo[k] <-> hi[k] for every pair, i.e. a[sigma(x)] = a[x].  A
+// tile holds every combination of the low bits and the high bits of the
+// pairs (<= 12 bits), so the tile maps onto itself: it is read into LDS with
+// the low bits contiguous and written back permuted, also with the low bits
+// contiguous -- both sides coalesced, no second state buffer.
+struct SwapArgs {
+    int32_t npairs, tbits;
+    int32_t lo[6], hi[6];
+    uint64_t tilemask, outmask;
+};
+
+__device__ __forceinline__ uint32_t extract_bits(uint64_t x, uint64_t mask)
+{
+    uint32_t r = 0;
+    int k = 0;
+    while (mask) {
+        const int p = __builtin_ctzll(mask);
+        r |= (uint32_t)((x >> p) & 1ull) << k++;
+        mask &= mask - 1;
+    }
+    return r;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_swap_bits(c2_t<R> *__restrict__ a, SwapArgs S)
+{
+    using V = c2_t<R>;
+    extern __shared__ char smem_raw[];
+    V *lds = reinterpret_cast<V *>(smem_raw);
+    const uint64_t base = deposit(blockIdx.x, S.outmask);
+    const uint32_t ntile = 1u << S.tbits;
+    for (uint32_t i = threadIdx.x; i < ntile; i += kBlock) lds[i] = a[base | deposit(i, S.tilemask)];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ntile; i += kBlock) {
+        const uint64_t y = base | deposit(i, S.tilemask);
+        uint64_t x = y;
+        for (int k = 0; k < S.npairs; ++k)
+            if (((y >> S.lo[k]) ^ (y >> S.hi[k])) & 1ull) x ^= (1ull << S.lo[k]) | (1ull << S.hi[k]);
+        a[y] = lds[extract_bits(x, S.tilemask)];
+    }
+}
+
+// <a|b> with b stored under another qubit layout: element i of a pairs with
+// element pi(i) of b (bit p of i -> bit map[p]).
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kBlock) void k_inner_perm_partial(const c2_t<RA> *__restrict__ a,
+                                                               const c2_t<RB> *__restrict__ b, uint64_t len,
+                                                               PermArgs P, double2 *__restrict__ part)
+{
+    __shared__ double sre[kBlock], sim[kBlock];
+    double re = 0.0, im = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < len; x += stride) {
+        uint64_t y = 0;
+        for (int p = 0; p < P.n; ++p) y |= ((x >> p) & 1ull) << P.perm[p];
+        const double ar = (double)a[x].x, ai = (double)a[x].y;
+        const double br = (double)b[y].x, bi = (double)b[y].y;
+        re += ar * br + ai * bi;
+        im += ar * bi - ai * br;
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = kBlock / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sre[0], sim[0]);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_gather(const c2_t<R> *__restrict__ a, const uint64_t *__restrict__ idx,
                                                    uint64_t m, double2 *__restrict__ out)
@@ -415,6 +489,47 @@ hipError_t launch_inner(const void *a, const void *b, int n, double *out, double
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_swap_bits(void *state, int n, const int *lo, const int *hi, int npairs, hipStream_t s)
+{
+    if (npairs < 0 || npairs > 6 || n < 1 || n > 40) return hipErrorInvalidValue;
+    if (npairs == 0) return hipSuccess;
+    const int low = n < 6 ? n : 6;
+    SwapArgs S{};
+    S.npairs = npairs;
+    uint64_t tm = (1ull << low) - 1;
+    for (int k = 0; k < npairs; ++k) {
+        if (lo[k] < 0 || lo[k] >= low || hi[k] < low || hi[k] >= n) return hipErrorInvalidValue;
+        S.lo[k] = lo[k];
+        S.hi[k] = hi[k];
+        tm |= 1ull << hi[k];
+    }
+    S.tilemask = tm;
+    S.tbits = __builtin_popcountll(tm);
+    S.outmask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~tm;
+    const uint64_t blocks = 1ull << (n - S.tbits);
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    const size_t lds = sizeof(c2_t<R>) << S.tbits;
+    k_swap_bits<R><<<(uint32_t)blocks, kBlock, lds, s>>>((c2_t<R> *)state, S);
+    return hipGetLastError();
+}
+
+template <typename RA, typename RB>
+hipError_t launch_inner_perm(const void *a, const void *b, int n, const int *map, double *out, double *scratch,
+                             hipStream_t s)
+{
+    const uint64_t len = 1ull << n;
+    PermArgs P{};
+    P.n = n;
+    for (int p = 0; p < n; ++p) P.perm[p] = map[p];
+    uint32_t nb = blocks_for(len, kBlock * 8);
+    if (nb > kInnerBlocks) nb = kInnerBlocks;
+    k_inner_perm_partial<RA, RB><<<nb, kBlock, 0, s>>>((const c2_t<RA> *)a, (const c2_t<RB> *)b, len, P,
+                                                       (double2 *)scratch);
+    k_inner_final<<<1, kBlock, 0, s>>>((const double2 *)scratch, nb, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s)
 {
     const uint64_t n16 = bytes / 16;
@@ -431,12 +546,21 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s
     template hipError_t launch_kron<R>(void *, const void *, int, const void *, int, hipStream_t);      \
     template hipError_t launch_perm<R>(void *, const void *, int, const int *, hipStream_t);            \
     template hipError_t launch_gather<R>(const void *, const uint64_t *, uint64_t, double *, hipStream_t); \
-    template hipError_t launch_marginal<R>(const void *, int, const int *, int, double *, double *, hipStream_t);
+    template hipError_t launch_marginal<R>(const void *, int, const int *, int, double *, double *, hipStream_t); \
+    template hipError_t launch_swap_bits<R>(void *, int, const int *, const int *, int, hipStream_t);
 QS_INST(double)
 QS_INST(float)
 template hipError_t launch_inner<double, double>(const void *, const void *, int, double *, double *, hipStream_t);
 template hipError_t launch_inner<double, float>(const void *, const void *, int, double *, double *, hipStream_t);
 template hipError_t launch_inner<float, double>(const void *, const void *, int, double *, double *, hipStream_t);
 template hipError_t launch_inner<float, float>(const void *, const void *, int, double *, double *, hipStream_t);
+template hipError_t launch_inner_perm<double, double>(const void *, const void *, int, const int *, double *, double *,
+                                                      hipStream_t);
+template hipError_t launch_inner_perm<double, float>(const void *, const void *, int, const int *, double *, double *,
+                                                     hipStream_t);
+template hipError_t launch_inner_perm<float, double>(const void *, const void *, int, const int *, double *, double *,
+                                                     hipStream_t);
+template hipError_t launch_inner_perm<float, float>(const void *, const void *, int, const int *, double *, double *,
+                                                    hipStream_t);
 
 }  // namespace qs

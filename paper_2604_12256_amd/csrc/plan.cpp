@@ -390,41 +390,171 @@ struct Builder {
     // of its qubits is blocked and its locally-needed qubits fit; otherwise all
     // its qubits become blocked.  Diagonal gates and block-selecting (control)
     // qubits need not be local: inside a chunk the other bits are constants.
+    // One greedy stage (gate block search with limit C) over the remaining
+    // gates: the local set starts with the always-local low bits; a gate
+    // joins when none of its qubits is blocked and the qubits it needs fit.
+    struct Masks {
+        std::vector<uint64_t> qs, nd;   // per gate: all qubits, qubits needed locally
+    };
+
+    static uint64_t permute_mask(uint64_t m, const std::vector<int> &sigma)
+    {
+        uint64_t out = 0;
+        for (size_t q = 0; q < sigma.size(); ++q)
+            if ((m >> q) & 1) out |= 1ull << sigma[q];
+        return out;
+    }
+
+    void greedy_stage(const Masks &M, const std::vector<int> &rem, int C, int low, int r, uint64_t *Lout,
+                      std::vector<int> *take, std::vector<int> *left) const
+    {
+        uint64_t L = (1ull << low) - 1;
+        uint64_t blocked = 0;
+        for (int gi : rem) {
+            const uint64_t qs = M.qs[gi];
+            const uint64_t nd = M.nd[gi];
+            if ((qs & blocked) || popc(nd) > r) {
+                blocked |= qs;
+                if (left) left->push_back(gi);
+                continue;
+            }
+            if (popc(L | nd) <= C) {
+                L |= nd;
+                if (take) take->push_back(gi);
+            } else {
+                blocked |= qs;
+                if (left) left->push_back(gi);
+            }
+        }
+        *Lout = L;
+    }
+
+    // Gates consumed by the next `horizon` greedy stages.
+    size_t lookahead(const Masks &M, std::vector<int> rem, int C, int low, int r, int horizon) const
+    {
+        size_t consumed = 0;
+        for (int h = 0; h < horizon && !rem.empty(); ++h) {
+            if (popc(M.nd[rem.front()]) > r) {
+                rem.erase(rem.begin());
+                ++consumed;
+                continue;
+            }
+            uint64_t L;
+            std::vector<int> take, left;
+            greedy_stage(M, rem, C, low, r, &L, &take, &left);
+            consumed += take.size();
+            rem.swap(left);
+        }
+        return consumed;
+    }
+
+    static void swap_qubits(Operator &g, const std::vector<int> &sigma)
+    {
+        for (int &q : g.q) q = sigma[q];
+    }
+
+    // Qubit reordering (Sec. 2.3): the low physical bits are local in every
+    // stage (coalescing), so qubits that the coming gates need often should
+    // sit there.  Candidate: swap the least-needed low bits with the
+    // most-needed high bits of a window of upcoming gates; accepted when the
+    // lookahead consumes enough more gates in the same number of stages to
+    // repay the permutation pass.  Free when the state is still |0...0>.
+    bool maybe_remap(std::vector<Operator> &pg, Masks &M, const std::vector<int> &rem, int nb, int C, int low,
+                     int r)
+    {
+        const int kWindow = 400, kHorizon = 6;
+        std::vector<double> freq(nb, 0.0);
+        int cnt = 0;
+        for (int gi : rem) {
+            if (cnt++ >= kWindow) break;
+            const uint64_t nd = M.nd[gi];
+            for (int q = 0; q < nb; ++q)
+                if ((nd >> q) & 1) freq[q] += 1.0;
+        }
+        std::vector<int> lows, highs;
+        for (int q = 0; q < low; ++q) lows.push_back(q);
+        for (int q = low; q < nb; ++q) highs.push_back(q);
+        std::stable_sort(lows.begin(), lows.end(), [&](int a, int b) { return freq[a] < freq[b]; });
+        std::stable_sort(highs.begin(), highs.end(), [&](int a, int b) { return freq[a] > freq[b]; });
+        std::vector<int> sigma(nb);
+        for (int q = 0; q < nb; ++q) sigma[q] = q;
+        int pairs = 0;
+        for (size_t i = 0; i < lows.size() && i < highs.size(); ++i) {
+            if (freq[highs[i]] <= freq[lows[i]] + 1.0) break;
+            sigma[lows[i]] = highs[i];
+            sigma[highs[i]] = lows[i];
+            ++pairs;
+        }
+        if (!pairs) return false;
+        const size_t c0 = lookahead(M, rem, C, low, r, kHorizon);
+        Masks T = M;
+        for (int gi : rem) {
+            T.qs[gi] = permute_mask(M.qs[gi], sigma);
+            T.nd[gi] = permute_mask(M.nd[gi], sigma);
+        }
+        const size_t c1 = lookahead(T, rem, C, low, r, kHorizon);
+        bool fresh = false;
+        for (auto it = plan.ops.rbegin(); it != plan.ops.rend(); ++it)
+            if (it->buffer == 0) {
+                fresh = it->kind == SIM_OP_INIT;
+                break;
+            }
+        // stages saved over the horizon ~ kHorizon * (1 - c0 / c1); a pass costs one
+        const double saved = c1 > 0 ? kHorizon * (1.0 - double(c0) / double(c1)) : 0.0;
+        if (!(c1 > c0 && (fresh || saved >= 1.5))) return false;
+        M.qs.swap(T.qs);
+        M.nd.swap(T.nd);
+        for (int gi : rem) swap_qubits(pg[gi], sigma);
+        std::vector<int> &lay = plan.layout;  // logical -> physical
+        for (int &p : lay) p = sigma[p];
+        if (!fresh) {
+            PlanOp op;
+            op.kind = SIM_OP_PERM;
+            op.buffer = 0;
+            op.buffer_qubits = nb;
+            op.perm = sigma;  // source bit p -> destination bit sigma[p] (a product of swaps)
+            const double amps = std::ldexp(1.0, nb);
+            op.bytes = 2.0 * amps * amp_bytes();
+            plan.stats.full_passes += 1;
+            plan.stats.bytes += op.bytes;
+            plan.stats.n_perm += 1;
+            plan.ops.push_back(std::move(op));
+        }
+        return true;
+    }
+
     void stages(int buffer, int nb, const std::vector<Operator> &gates)
     {
         const int C = std::min<int>((int)o.C, nb), r = o.reg_bits;
         const int low = std::min(o.fixed_low, C);
+        // gates on physical qubits of the buffer (the full state may be remapped)
+        std::vector<Operator> pg = gates;
+        if (buffer == 0)
+            for (Operator &g : pg)
+                for (int &q : g.q) q = plan.layout[q];
         std::vector<int> rem(gates.size());
         for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
+        Masks M;
+        M.qs.resize(pg.size());
+        M.nd.resize(pg.size());
+        for (size_t i = 0; i < pg.size(); ++i) {
+            M.qs[i] = pg[i].mask();
+            M.nd[i] = tile_need(pg[i]);
+        }
         const double nb_amps = std::ldexp(1.0, nb);
+        const bool remap = buffer == 0 && (o.opt & SIM_OPT_REMAP) && nb > C;
         while (!rem.empty()) {
-            const Operator &first = gates[rem.front()];
-            if (popc(tile_need(first)) > r) {  // beyond the register tile: one full pass
+            if (remap) maybe_remap(pg, M, rem, nb, C, low, r);
+            const Operator &first = pg[rem.front()];
+            if (popc(M.nd[rem.front()]) > r) {  // beyond the register tile: one full pass
                 add_full_pass_op(buffer, nb, first);
                 account_full_pass(buffer, nb, first);
                 rem.erase(rem.begin());
                 continue;
             }
-            uint64_t L = (1ull << low) - 1;
-            uint64_t blocked = 0;
+            uint64_t L;
             std::vector<int> take, left;
-            for (int gi : rem) {
-                const Operator &g = gates[gi];
-                const uint64_t qs = g.mask();
-                const uint64_t nd = tile_need(g);
-                if ((qs & blocked) || popc(nd) > r) {
-                    blocked |= qs;
-                    left.push_back(gi);
-                    continue;
-                }
-                if (popc(L | nd) <= C) {
-                    L |= nd;
-                    take.push_back(gi);
-                } else {
-                    blocked |= qs;
-                    left.push_back(gi);
-                }
-            }
+            greedy_stage(M, rem, C, low, r, &L, &take, &left);
             for (int q = 0; q < nb && popc(L) < C; ++q) L |= 1ull << q;
             PlanOp st;
             st.kind = SIM_OP_STAGE;
@@ -433,7 +563,7 @@ struct Builder {
             for (int q = 0; q < nb; ++q)
                 if ((L >> q) & 1) st.local.push_back(q);
             double fpa = 0;
-            std::vector<int> over = make_phases(st, gates, take, &fpa);
+            std::vector<int> over = make_phases(st, pg, take, &fpa);
             st.flops = fpa * nb_amps;
             st.bytes = 2.0 * nb_amps * amp_bytes();
             plan.stats.flops += st.flops;
@@ -540,6 +670,7 @@ struct Builder {
         if ((o.opt & SIM_OPT_DIAG) && (o.opt & SIM_OPT_STAGES)) {
             const size_t mark = plan.ops.size();
             const PlanStats saved = plan.stats;
+            const std::vector<int> saved_layout = plan.layout;
             uint64_t v = 0;
             std::vector<Operator> dd = diagonal_detector(nb, (int)o.D, gates, &v);
             lower_gates(buffer, nb, std::move(dd));
@@ -549,7 +680,9 @@ struct Builder {
                                         std::make_move_iterator(plan.ops.end()));
             plan.ops.resize(mark);
             const PlanStats stats_dd = plan.stats;
+            const std::vector<int> layout_dd = plan.layout;
             plan.stats = saved;
+            plan.layout = saved_layout;
             lower_gates(buffer, nb, gates);
             double t_plain = 0;
             for (size_t i = mark; i < plan.ops.size(); ++i) t_plain += est_seconds(plan.ops[i]);
@@ -557,6 +690,7 @@ struct Builder {
                 plan.ops.resize(mark);
                 for (PlanOp &op : with_dd) plan.ops.push_back(std::move(op));
                 plan.stats = stats_dd;
+                plan.layout = layout_dd;
             }
             plan.stats.dd_visits += v;
             return;

@@ -22,8 +22,8 @@ KIND = {"U": 0, "MATRIX": 0, "DIAG": 1, "H": 2, "X": 3, "Y": 4, "Z": 5, "S": 6, 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(6)
 STATUS = {0: "OK", 1: "INVAL", 2: "NOMEM", 3: "DEVICE", 4: "STATE", 5: "UNSUPPORTED"}
 # optimisation flags
-OPT_DIAG, OPT_FUSE, OPT_STAGES, OPT_BOOST = 1, 2, 4, 8
-OPT_ALL = 15
+OPT_DIAG, OPT_FUSE, OPT_STAGES, OPT_BOOST, OPT_REMAP = 1, 2, 4, 8, 16
+OPT_ALL = 31
 # plan op kinds
 OP_NAMES = {0: "INIT", 1: "KRON", 2: "DENSE", 3: "DIAG", 4: "STAGE", 5: "PERM"}
 DTYPES = {"c128": 0, "c64": 1}

@@ -12,7 +12,7 @@ from paper_2604_12256_amd.workloads import Gate
 
 from .planinterp import access_count, run_plan
 
-ALL_OPTS = list(range(16))
+ALL_OPTS = list(range(16)) + [31, 16 | 4, 16 | 6, 16 | 12, 16 | 14]
 
 
 def plan_state(n, gates, **kw):
@@ -256,3 +256,45 @@ def test_invalid_gates_rejected():
         qsim.Plan(3, [Gate("U", (0,), 0.0, np.array([[1, 1], [0, 1]], dtype=complex))])
     with pytest.raises(qsim.QsimError):
         qsim.Plan(3, [Gate("DIAG", (0,), 0.0, np.array([1, 2], dtype=complex))])
+
+
+# ---------------------------------------------------------------- qubit reordering (Sec. 2.3)
+def high_qubit_circuit(n, offset, layers_lo, layers_hi, seed):
+    """Entangle every qubit, then work only on the top qubits (the always-local
+    low bits are idle there, so moving hot qubits down pays)."""
+    g = W.layered(n, layers_lo, seed)
+    g += [Gate(x.kind, tuple(q + offset for q in x.qubits), x.theta, x.data)
+          for x in W.layered(n - offset, layers_hi, seed + 1)]
+    return g
+
+
+def test_remap_emits_permutation_and_matches_oracle(oracle_mod):
+    n = 14
+    gates = high_qubit_circuit(n, 6, 2, 12, 5)
+    p = qsim.Plan(n, gates, opt=qsim.OPT_ALL, C=10)
+    ops = p.ops()
+    perms = [o for o in ops if o["kind"] == "PERM"]
+    assert perms, "expected a qubit permutation"
+    for o in perms:  # products of swaps of low (< 6) and high bits
+        for src, dst in enumerate(o["perm"]):
+            assert o["perm"][dst] == src
+            if src != dst:
+                assert (src < 6) != (dst < 6)
+    assert p.layout() != list(range(n))
+    want = oracle_mod.run(n, gates)
+    assert np.max(np.abs(run_plan(ops, n, p.layout()) - want)) < 1e-12
+    # fewer full passes than without reordering
+    q = qsim.Plan(n, gates, opt=qsim.OPT_ALL & ~qsim.OPT_REMAP, C=10)
+    assert p.stats()["full_passes"] < q.stats()["full_passes"]
+
+
+def test_remap_free_relabel_at_start():
+    """From |0...0> a relabelling costs nothing: no PERM op, layout changed."""
+    n = 30
+    gates = [Gate(x.kind, tuple(q + 10 for q in x.qubits), x.theta, x.data) for x in W.layered(20, 10, 3)]
+    opt = qsim.OPT_STAGES | qsim.OPT_FUSE | qsim.OPT_REMAP
+    p = qsim.Plan(n, gates, opt=opt)
+    assert not [o for o in p.ops() if o["kind"] == "PERM"]
+    assert p.layout() != list(range(n))
+    q = qsim.Plan(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE)
+    assert p.stats()["full_passes"] < q.stats()["full_passes"]

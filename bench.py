@@ -73,7 +73,24 @@ def run_workload(name, dtype, opt, steps, warmup, profile=True):
             "per_kind": per_kind, "stats": st, "norm": norm}
 
 
-def roofline(per_kind, dtype):
+def measured_traffic(kernel, workload, dtype):
+    """HBM bytes per launch of the kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a copy kernel of known size),
+    only while the kernel source is the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{dtype}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2604_12256_amd", "csrc", "kernel_stage.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return round(rec["traffic_bytes_per_launch"])
+
+
+def roofline(per_kind, dtype, workload=None):
     kind = max(per_kind, key=lambda k: per_kind[k]["ms"])
     d = per_kind[kind]
     avg_s = d["ms"] / d["launches"] / 1e3
@@ -94,8 +111,29 @@ def roofline(per_kind, dtype):
                          "INIT": "k_init"}.get(kind, kind),
               "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": d["launches"] // max(1, 1),
               "flops_per_launch": flops, "bytes_per_launch": byts,
-              "hbm_GBps_of_kernel": round(byts / avg_s / 1e9, 1), "traffic": None})
+              "hbm_GBps_of_kernel": round(byts / avg_s / 1e9, 1),
+              "traffic": measured_traffic("k_stage", workload, dtype) if kind == "STAGE" and workload else None})
     return r
+
+
+def copy_reference(gib=16, reps=3):
+    """Achievable HBM bandwidth: the library's plain copy kernel (K11) on
+    `gib` GiB, read + write bytes / time."""
+    import torch
+    from paper_2604_12256_amd import qsim
+    a = torch.zeros(gib << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        qsim.device_copy(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * a.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return round(best, 1)
 
 
 def cpu_baseline(name, n_prefix):
@@ -165,9 +203,10 @@ def main():
         "stages": st["n_stages"],
         "plan_flops": st["flops"],
         "norm_error": abs(r["norm"] - 1.0),
-        "roofline": roofline(r["per_kind"], args.dtype),
+        "roofline": roofline(r["per_kind"], args.dtype, args.workload),
         "per_kind_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in r["per_kind"].items()},
     }
+    out["hbm_copy_GBps"] = copy_reference()
     if not args.no_secondary:
         d = run_workload("diag30", "c128", qsim.OPT_ALL, 3, 1)
         ms = d["wall_s"] / 3 * 1e3

@@ -112,6 +112,7 @@ typedef struct {
     double run_ms;             /* device time of the last sim_run (HIP events) */
     double algorithmic_bytes;  /* bytes the plan moves over the full state */
     double flops;              /* floating-point operations of the plan (estimate) */
+    double est_ms;             /* device time of the plan predicted by the optimiser's cost model */
 } sim_run_stats;
 
 /* Create a context for an n_qubits state of the given dtype.

@@ -501,6 +501,7 @@ void fill_stats(const qs::Plan &P, uint64_t n_gates, sim_run_stats *s)
     s->plan_ms = P.stats.plan_ms;
     s->algorithmic_bytes = P.stats.bytes;
     s->flops = P.stats.flops;
+    s->est_ms = P.stats.est_ms;
 }
 
 }  // namespace

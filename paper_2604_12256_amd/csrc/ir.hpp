@@ -86,12 +86,13 @@ struct PlanOp {
     std::vector<Phase> phases;        // kernel program
     double flops = 0;                 // floating-point operations of the op
     double bytes = 0;                 // algorithmic HBM bytes of the op
+    double est_s = 0;                 // STAGE: modelled device seconds of its operators
 };
 
 struct PlanStats {
     uint64_t full_passes = 0, write_passes = 0, n_stages = 0, n_dense = 0, n_diag = 0,
              n_kron = 0, n_perm = 0, n_subruns = 0, n_ops = 0;
-    double bytes = 0, flops = 0, plan_ms = 0;
+    double bytes = 0, flops = 0, plan_ms = 0, est_ms = 0;
     uint64_t dd_visits = 0, booster_gates = 0, booster_groups = 0;
 };
 

@@ -26,9 +26,21 @@ int popc(uint64_t x) { return __builtin_popcountll(x); }
 // diagonal one complex multiply per amplitude).
 double op_cost(bool diag, int dense_qubits)
 {
-    if (diag) return 4.0 / 0.5;
+    if (diag) return 4.0 / 0.4;
     static const double eff[] = {1.0, 0.5, 0.6, 0.4, 0.28, 0.3};
     return 4.0 * double(1 << dense_qubits) / eff[dense_qubits < 5 ? dense_qubits : 5];
+}
+
+// Device seconds of one stage-kernel operator on 2^30 complex128
+// amplitudes, from microbenchmarks of the stage kernel on MI355X (about 1/27
+// microsecond per op_cost unit); complex64 halves the arithmetic.
+double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64)
+{
+    const double scale = amps / 1073741824.0 * (c64 ? 0.5 : 1.0);
+    const double unit = 27e-6;
+    if (k.type == KOp::DIAG) return scale * unit * (op_cost(true, 0) + (k.dq.size() > 2 ? 3.0 : 0.0));
+    const int kr = __builtin_popcount(k.reg_mask);
+    return scale * unit * op_cost(false, kr >= 3 ? reg_bits : kr);
 }
 // Floating-point operations per amplitude: a dense k-qubit operator does 2^k
 // complex multiply-adds (8 flops each), a diagonal one complex multiply (6).
@@ -251,6 +263,31 @@ struct Builder {
             }
             B = Block();
         };
+        // Several blocks stay open at once, one per disjoint set of register
+        // qubits; they may share selector qubits only, so open blocks commute
+        // and a gate can join the block that owns its register qubits even
+        // when other blocks were opened after it.  A gate bridging two blocks
+        // closes them.
+        std::vector<Block> open;
+        auto close_all_owning = [&](uint32_t S, const std::vector<int> &T) {
+            for (size_t i = 0; i < open.size();) {
+                bool hit = (open[i].S & S) != 0;
+                // a selector of the new gate that is a register qubit of a block
+                // (never, selectors are non-register) or a register qubit of the
+                // gate that is a selector of a block: the block uses it as a
+                // control, which does not commute with the gate
+                for (int t : open[i].T)
+                    for (int b = 0; b < r; ++b)
+                        if (((S >> b) & 1) && reg_phys[b] == t) hit = true;
+                (void)T;
+                if (hit) {
+                    emit(open[i]);
+                    open.erase(open.begin() + i);
+                } else {
+                    ++i;
+                }
+            }
+        };
         for (const Operator *gp : gates) {
             const Operator &g = *gp;
             uint32_t gS = 0;
@@ -261,32 +298,46 @@ struct Builder {
                 else gT.push_back(x);
             }
             if (g.diag && g.k() > 3) {  // a wide diagonal (diagonal detector output): its own table
-                emit(F);
+                close_all_owning(gS, gT);
                 push_diag(g.q, g.m);
                 continue;
             }
             const double gcost = g.diag ? op_cost(true, 0) : dense_cost(gS);
-            if (F.open) {
-                const uint32_t S2 = F.S | gS;
-                std::vector<int> T2 = F.T;
+            // blocks owning a register qubit of g
+            std::vector<size_t> own;
+            for (size_t i = 0; i < open.size(); ++i)
+                if (open[i].S & gS) own.push_back(i);
+            if (fuse && own.size() == 1) {
+                Block &B = open[own[0]];
+                const uint32_t S2 = B.S | gS;
+                std::vector<int> T2 = B.T;
                 for (int x : gT)
                     if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
-                const bool diag2 = F.acc.diag && g.diag;
+                const bool diag2 = B.acc.diag && g.diag;
                 const double fused = diag2 ? op_cost(true, 0) : dense_cost(S2);
                 const bool sel_ok = diag2 ? (int)T2.size() <= kTmaxUniform
                                           : (lane_sel(T2) ? ((int)T2.size() <= kTmaxLane && popc(kernel_mask(S2)) <= 2)
                                                           : (int)T2.size() <= kTmaxUniform);
-                if (fuse && sel_ok && fused <= F.indiv + gcost + 1e-9) {
+                // a register qubit g adds to B must not be another block's selector
+                bool clash = false;
+                for (size_t i = 0; i < open.size(); ++i) {
+                    if (i == own[0]) continue;
+                    for (int t : open[i].T)
+                        for (int b = 0; b < r; ++b)
+                            if (((gS >> b) & 1) && reg_phys[b] == t) clash = true;
+                }
+                if (!clash && sel_ok && fused <= B.indiv + gcost + 1e-9) {
                     std::vector<int> l2 = qlist(S2, T2);
-                    if (l2 != F.acc.q) F.acc = embed(F.acc, l2);
-                    apply_left(F.acc, g);
-                    F.S = S2;
-                    F.T = T2;
-                    F.indiv += gcost;
+                    if (l2 != B.acc.q) B.acc = embed(B.acc, l2);
+                    apply_left(B.acc, g);
+                    B.S = S2;
+                    B.T = T2;
+                    B.indiv += gcost;
                     continue;
                 }
-                emit(F);
             }
+            // g starts a block of its own: close every block it does not commute with
+            close_all_owning(gS, gT);
             const bool alone_ok = g.diag ? (int)gT.size() <= kTmaxUniform
                                          : (lane_sel(gT) ? ((int)gT.size() <= kTmaxLane && popc(kernel_mask(gS)) <= 2)
                                                          : (int)gT.size() <= kTmaxUniform);
@@ -297,13 +348,19 @@ struct Builder {
                 }
                 throw std::runtime_error("fuse_phase: dense gate needs more register bits");
             }
-            F.open = true;
-            F.S = gS;
-            F.T = gT;
-            F.acc = embed(g, qlist(gS, gT));
-            F.indiv = gcost;
+            Block nb;
+            nb.open = true;
+            nb.S = gS;
+            nb.T = gT;
+            nb.acc = embed(g, qlist(gS, gT));
+            nb.indiv = gcost;
+            if (!fuse || gS == 0) {  // no fusion, or a phase on non-register bits only: emit now
+                emit(nb);
+                continue;
+            }
+            open.push_back(std::move(nb));
         }
-        emit(F);
+        for (Block &B : open) emit(B);
     }
 
     // Register phases of one stage: gate block search with limit r on the
@@ -377,6 +434,8 @@ struct Builder {
                 st.gates.push_back(all[gi]);
             }
             fuse_phase(ph, tg, reg_phys, lane_phys, &fpa);
+            for (const KOp &k : ph.ops) st.est_s += kop_seconds(k, r, std::ldexp(1.0, st.buffer_qubits),
+                                                                plan.dtype == SIM_C64);
             st.phases.push_back(std::move(ph));
             prev = st.phases.back().reg;
             rem.swap(left);
@@ -657,6 +716,7 @@ struct Builder {
     // plus a launch overhead.
     static double est_seconds(const PlanOp &op)
     {
+        if (op.kind == SIM_OP_STAGE) return op.bytes / 5.5e12 + op.est_s + 4e-6;
         return std::max(op.bytes / 5.5e12, op.flops / 55e12) + 4e-6;
     }
 
@@ -854,6 +914,8 @@ void build_plan(Plan &plan, const std::vector<Operator> &gates)
     }
     b.lower(0, plan.n, std::move(rest));
     plan.stats.n_ops = plan.ops.size();
+    for (const PlanOp &op : plan.ops)
+        if (op.buffer == 0) plan.stats.est_ms += 1e3 * Builder::est_seconds(op);
     auto t1 = std::chrono::steady_clock::now();
     plan.stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 }

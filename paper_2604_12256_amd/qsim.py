@@ -45,7 +45,7 @@ class SimRunStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("n_gates", "n_ops", "full_passes", "write_passes",
                                                 "read_passes", "n_stages", "n_dense", "n_diag", "n_kron",
                                                 "n_perm", "n_subruns")] + \
-               [(f, ctypes.c_double) for f in ("plan_ms", "run_ms", "algorithmic_bytes", "flops")]
+               [(f, ctypes.c_double) for f in ("plan_ms", "run_ms", "algorithmic_bytes", "flops", "est_ms")]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -269,6 +269,32 @@ struct Builder {
         // when other blocks were opened after it.  A gate bridging two blocks
         // closes them.
         std::vector<Block> open;
+        // Diagonal gates on non-register qubits only commute with every open
+        // block (blocks are diagonal in their selector qubits): they are
+        // collected into one diagonal per phase, emitted when it grows too
+        // wide or at the end of the phase.
+        Block Z;
+        const int kZmax = 10;
+        auto z_add = [&](const Operator &g) {
+            std::vector<int> T2 = Z.open ? Z.T : std::vector<int>();
+            for (int x : g.q)
+                if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
+            if (Z.open && (int)T2.size() > kZmax) {
+                emit(Z);
+                T2.assign(g.q.begin(), g.q.end());
+            }
+            if (!Z.open) {
+                Z.open = true;
+                Z.S = 0;
+                Z.T = T2;
+                Z.acc = embed(g, T2);
+                Z.indiv = op_cost(true, 0);
+                return;
+            }
+            if (T2 != Z.acc.q) Z.acc = embed(Z.acc, T2);
+            apply_left(Z.acc, g);
+            Z.T = T2;
+        };
         auto close_all_owning = [&](uint32_t S, const std::vector<int> &T) {
             for (size_t i = 0; i < open.size();) {
                 bool hit = (open[i].S & S) != 0;
@@ -348,6 +374,10 @@ struct Builder {
                 }
                 throw std::runtime_error("fuse_phase: dense gate needs more register bits");
             }
+            if (fuse && gS == 0 && g.diag && g.k() <= kZmax) {
+                z_add(g);
+                continue;
+            }
             Block nb;
             nb.open = true;
             nb.S = gS;
@@ -361,6 +391,7 @@ struct Builder {
             open.push_back(std::move(nb));
         }
         for (Block &B : open) emit(B);
+        emit(Z);
     }
 
     // Register phases of one stage: gate block search with limit r on the

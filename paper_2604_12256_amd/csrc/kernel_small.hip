@@ -12,47 +12,22 @@ namespace {
 constexpr int kSmallThreads = 512;
 constexpr uint32_t kSmallLdsBytes = 128u * 1024u;
 
-template <typename R, int K>
-__device__ __forceinline__ void small_dense(c2_t<R> *s, int n, const GateDesc &g, const QS_CONST R *m)
-{
-    using V = c2_t<R>;
-    constexpr int D = 1 << K;
-    const uint64_t ng = 1ull << (n - K);
-    uint32_t offq[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int t = 0; t < K; ++t)
-            if ((r >> t) & 1) o |= 1u << g.q[t];
-        offq[r] = o;
-    }
-    for (uint64_t grp = threadIdx.x; grp < ng; grp += blockDim.x) {
-        const uint32_t base = (uint32_t)insert_zeros<K>(grp, g.sorted);
-        V v[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) v[c] = s[base | offq[c]];
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            V acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
-#pragma unroll
-            for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
-            s[base | offq[r]] = acc;
-        }
-    }
-}
-
+// Each thread owns the amplitudes i = tid + u * blockDim (u < kPer) and
+// computes their new values from the LDS state (output-stationary): for a
+// dense gate, out[i] = sum_c M[r(i)][c] s[base(i) | off(c)] where r(i)
+// collects the gate-qubit bits of i; all outputs are computed before any is
+// written back (one barrier), so register use does not grow with 2^k.
 template <typename R>
 __device__ __forceinline__ void run_small(const SmallItem &it)
 {
     using V = c2_t<R>;
+    constexpr int kPer = (kSmallLdsBytes / sizeof(V)) / kSmallThreads;  // 16 (c128) / 32 (c64)
     extern __shared__ char smem_raw[];
     V *s = reinterpret_cast<V *>(smem_raw);
     const int n = (int)it.n;
     const uint32_t len = 1u << n;
     V *gstate = reinterpret_cast<V *>(it.state);
-    const QS_CONST R *tables = as_const(reinterpret_cast<const R *>(it.tables));
-    const GateDesc *gates = it.gates;
+    const R *tables = reinterpret_cast<const R *>(it.tables);
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
         if (it.init) {
             V v;
@@ -65,22 +40,44 @@ __device__ __forceinline__ void run_small(const SmallItem &it)
     }
     __syncthreads();
     for (uint32_t gi = 0; gi < it.ngates; ++gi) {
-        const GateDesc g = gates[gi];
-        const QS_CONST R *m = tables + 2 * g.table;
-        if (g.diag) {
-            for (uint32_t x = threadIdx.x; x < len; x += blockDim.x) {
+        const GateDesc *g = it.gates + gi;
+        const uint32_t k = g->k;
+        const R *m = tables + 2 * g->table;
+        uint32_t gmask = 0;
+        for (uint32_t t = 0; t < k; ++t) gmask |= 1u << g->q[t];
+        if (g->diag) {
+            for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
                 uint32_t y = 0;
-                for (uint32_t t = 0; t < g.k; ++t) y |= ((x >> g.q[t]) & 1u) << t;
-                s[x] = cmul(s[x], ldc<R>(m, y));
+                for (uint32_t t = 0; t < k; ++t) y |= ((i >> g->q[t]) & 1u) << t;
+                s[i] = cmul(s[i], ldc<R>(m, y));
             }
         } else {
-            switch (g.k) {
-            case 1: small_dense<R, 1>(s, n, g, m); break;
-            case 2: small_dense<R, 2>(s, n, g, m); break;
-            case 3: small_dense<R, 3>(s, n, g, m); break;
-            case 4: small_dense<R, 4>(s, n, g, m); break;
-            case 5: small_dense<R, 5>(s, n, g, m); break;
-            default: small_dense<R, 6>(s, n, g, m); break;
+            const uint32_t d = 1u << k;
+            V out[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const uint32_t i = threadIdx.x + (uint32_t)u * blockDim.x;
+                if (i < len) {
+                    uint32_t r = 0;
+                    for (uint32_t t = 0; t < k; ++t) r |= ((i >> g->q[t]) & 1u) << t;
+                    const uint32_t base = i & ~gmask;
+                    V acc;
+                    acc.x = R(0);
+                    acc.y = R(0);
+                    for (uint32_t c = 0; c < d; ++c) {
+                        uint32_t o = base;
+                        for (uint32_t t = 0; t < k; ++t)
+                            if ((c >> t) & 1u) o |= 1u << g->q[t];
+                        cmac(acc, ldc<R>(m, (uint64_t)r * d + c), s[o]);
+                    }
+                    out[u] = acc;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const uint32_t i = threadIdx.x + (uint32_t)u * blockDim.x;
+                if (i < len) s[i] = out[u];
             }
         }
         __syncthreads();

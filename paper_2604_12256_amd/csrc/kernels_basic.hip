@@ -73,6 +73,36 @@ __global__ __launch_bounds__(kBlock) void k_dense(c2_t<R> *__restrict__ a, const
     }
 }
 
+// Six-qubit dense gate: a block stages four groups of 64 amplitudes in LDS
+// and every thread computes one output amplitude (one matrix row), so no
+// thread holds a whole group in registers.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_dense6(c2_t<R> *__restrict__ a, const R *__restrict__ m, uint64_t ngroups,
+                                                   GateDesc g)
+{
+    using V = c2_t<R>;
+    __shared__ V tile[kBlock];
+    const uint64_t grp = (uint64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+    const uint32_t r = threadIdx.x & 63;
+    const bool valid = grp < ngroups;
+    uint64_t base = 0, mine = 0;
+    if (valid) {
+        base = insert_zeros<6>(grp, g.sorted);
+        mine = base;
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+            if ((r >> t) & 1) mine |= 1ull << g.q[t];
+        tile[threadIdx.x] = a[mine];
+    }
+    __syncthreads();
+    if (valid) {
+        const V *in = tile + (threadIdx.x & ~63u);
+        V acc = cmul(ldc<R>(m, (uint64_t)r * 64), in[0]);
+        for (int c = 1; c < 64; ++c) cmac(acc, ldc<R>(m, (uint64_t)r * 64 + c), in[c]);
+        a[mine] = acc;
+    }
+}
+
 // Diagonal of 2^k entries over the qubits q[0..k): a[x] *= T[y], y collects
 // bit q[t] of x into bit t (Sec. 4.5: one complex multiply per amplitude).
 struct DiagArgs {
@@ -378,7 +408,9 @@ hipError_t launch_dense(void *state, int n, const GateDesc &g, const void *mat, 
     case 3: k_dense<R, 3><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
     case 4: k_dense<R, 4><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
     case 5: k_dense<R, 5><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
-    default: k_dense<R, 6><<<nb, kBlock, 0, s>>>(a, m, ng, g); break;
+    default:
+        k_dense6<R><<<blocks_for(ng, kBlock / 64), kBlock, 0, s>>>(a, (const R *)mat, ng, g);
+        break;
     }
     return hipGetLastError();
 }

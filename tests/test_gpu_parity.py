@@ -324,3 +324,59 @@ def test_batched_small_circuits(oracle_mod):
     for sim, want in sims:
         check64(sim.amplitudes(), want, oracle_mod, "batch c64")
         sim.close()
+
+
+def test_ghz_30q_closed_form():
+    """GHZ at 30 qubits: exactly two amplitudes of 1/sqrt(2)."""
+    n = 30
+    gates = [Gate("H", (0,))] + [Gate("CNOT", (q, q + 1)) for q in range(n - 1)]
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    idx = np.concatenate([np.array([0, (1 << n) - 1], dtype=np.uint64), W.sample_indices(n, 1 << 16, 4)])
+    got = sim.amplitudes(idx)
+    want = np.zeros(idx.size, dtype=np.complex128)
+    want[(idx == 0) | (idx == (1 << n) - 1)] = 1 / math.sqrt(2)
+    check128(got, want, "ghz30")
+    p = sim.probabilities([0, 29])
+    assert np.max(np.abs(p - np.array([0.5, 0, 0, 0.5]))) < 1e-13
+    sim.close()
+
+
+def test_circuit_times_inverse_28q():
+    """C * C^-1 = identity at full size: |0...0> comes back."""
+    from .test_oracle_pins import inverse_circuit
+    n, gates = W.config_circuit("layered28")
+    say("layered28 + inverse")
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates + inverse_circuit(gates))
+    sim.run()
+    idx = np.concatenate([np.array([0], dtype=np.uint64), W.sample_indices(n, 1 << 16, 6)])
+    got = sim.amplitudes(idx)
+    want = np.zeros(idx.size, dtype=np.complex128)
+    want[idx == 0] = 1
+    check128(got, want, "C C^-1")
+    assert abs(sim.norm() - 1) < 1e-12
+    sim.close()
+
+
+def test_served_results_equal_solo_runs():
+    """Serving loop: every request's final state equals its solo run (batched
+    small circuits and overlapping large ones)."""
+    from paper_2604_12256_amd import serve as S
+    reqs = W.serving_stream(24, 500.0, 7, n_min=8, n_max=18)
+    be = S.GpuBackend(qsim.OPT_ALL, n_streams=3, keep_states=True)
+    res = S.serve(reqs, be, max_streams=3)
+    assert sorted(r.rid for r in res) == sorted(r.rid for r in reqs)
+    assert any(r.mode == "batch" for r in res) and any(r.mode == "stream" for r in res)
+    for req in reqs:
+        solo = qsim.Simulator(req.n, dtype=req.dtype, opt=0)
+        solo.load(req.circuit())
+        solo.run()
+        a = solo.amplitudes()
+        b = be.kept[req.rid]
+        if req.dtype == "c128":
+            check128(b, a, f"served rid={req.rid}")
+        else:
+            assert 1 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real) <= 1e-6
+        solo.close()

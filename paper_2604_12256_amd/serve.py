@@ -98,7 +98,10 @@ class GpuBackend:
         return ev
 
     def start_batch(self, sims: Sequence) -> object:
-        self.qsim.run_batch(list(sims), stream=self.batch_stream)
+        for dtype in ("c128", "c64"):   # one launch per dtype, both on the batch stream
+            group = [s for s in sims if s.dtype == dtype]
+            if group:
+                self.qsim.run_batch(group, stream=self.batch_stream)
         ev = self.torch.cuda.Event()
         ev.record(self.batch_stream)
         return ev

@@ -90,7 +90,7 @@ def measured_traffic(kernel, workload, dtype):
     return round(rec["traffic_bytes_per_launch"])
 
 
-def roofline(per_kind, dtype, workload=None):
+def roofline(per_kind, dtype, steps, workload=None):
     kind = max(per_kind, key=lambda k: per_kind[k]["ms"])
     d = per_kind[kind]
     avg_s = d["ms"] / d["launches"] / 1e3
@@ -109,7 +109,7 @@ def roofline(per_kind, dtype, workload=None):
              "frac": round(ach / HBM_PEAK_GBS, 4)}
     r.update({"kernel": {"STAGE": "k_stage", "DENSE": "k_dense", "DIAG": "k_diag", "KRON": "k_kron",
                          "INIT": "k_init"}.get(kind, kind),
-              "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": d["launches"] // max(1, 1),
+              "avg_launch_ms": round(avg_s * 1e3, 4), "launches_per_step": d["launches"] // steps,
               "flops_per_launch": flops, "bytes_per_launch": byts,
               "hbm_GBps_of_kernel": round(byts / avg_s / 1e9, 1),
               "traffic": measured_traffic("k_stage", workload, dtype) if kind == "STAGE" and workload else None})
@@ -162,7 +162,7 @@ def main():
     ap.add_argument("--workload", default="layered30")
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-prefix", type=int, default=12)
+    ap.add_argument("--cpu-prefix", type=int, default=60)
     ap.add_argument("--no-secondary", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -203,7 +203,7 @@ def main():
         "stages": st["n_stages"],
         "plan_flops": st["flops"],
         "norm_error": abs(r["norm"] - 1.0),
-        "roofline": roofline(r["per_kind"], args.dtype, args.workload),
+        "roofline": roofline(r["per_kind"], args.dtype, args.steps, args.workload),
         "per_kind_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in r["per_kind"].items()},
     }
     out["hbm_copy_GBps"] = copy_reference()
@@ -216,7 +216,7 @@ def main():
                             "gate_apps_per_s": round(d["gates"] / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
                             "hbm_GBps": round(dh, 1), "hbm_frac": round(dh / HBM_PEAK_GBS, 4),
                             "full_passes": d["stats"]["full_passes"],
-                            "roofline": roofline(d["per_kind"], "c128")}
+                            "roofline": roofline(d["per_kind"], "c128", 3)}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_prefix)

@@ -60,7 +60,9 @@ Options resolve_options(const sim_options *o, sim_dtype dtype, int n)
         r.force_fuse_k = o->force_fuse_k;
     }
     r.reg_bits = dtype == SIM_C128 ? 4 : 5;
-    if (r.C == 0) r.C = dtype == SIM_C128 ? 13 : 14;
+    // Default chunk: 2^12 complex128 / 2^13 complex64 amplitudes (64 KiB), so two
+    // workgroups share a CU and one's HBM load/store overlaps the other's compute.
+    if (r.C == 0) r.C = dtype == SIM_C128 ? 12 : 13;
     if (r.F > 6) r.F = 6;
     if (r.D > 20) r.D = 20;
     if (r.D < 1) r.D = 1;

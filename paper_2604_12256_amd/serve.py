@@ -27,6 +27,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import sys
 import time
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Sequence
@@ -134,8 +135,9 @@ class _Slot:
 
 
 def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypass: int = 8,
-          poll_s: float = 2e-4) -> List[Result]:
-    """Runs the request stream through the continuous-batching server."""
+          poll_s: float = 2e-4, progress=None) -> List[Result]:
+    """Runs the request stream through the continuous-batching server.
+    `progress(n_done, n_total)` is called after each completion, if given."""
     pending = sorted(requests, key=lambda r: r.arrival_s)
     results: Dict[int, Result] = {r.rid: Result(r.rid, r.n, r.dtype, 0, r.arrival_s) for r in pending}
     queue: List[W.Request] = []
@@ -206,6 +208,8 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
                 running.remove(slot)
                 n_done += 1
                 progressed = True
+                if progress:
+                    progress(n_done, len(pending))
         if batch is not None and backend.done(batch_token):
             t = backend.now()
             for s in batch:
@@ -213,6 +217,8 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
                 backend.release(s.req.rid, s.handle)
                 used -= state_bytes(s.req.n, s.req.dtype)
                 n_done += 1
+                if progress:
+                    progress(n_done, len(pending))
             batch, batch_token = None, None
             progressed = True
         if not progressed:
@@ -220,7 +226,7 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
     return [results[r.rid] for r in pending]
 
 
-def serve_sequential_plain(requests: Sequence[W.Request], backend) -> List[Result]:
+def serve_sequential_plain(requests: Sequence[W.Request], backend, progress=None) -> List[Result]:
     """Baseline: FIFO, one request at a time, gate-by-gate path."""
     out = []
     for req in sorted(requests, key=lambda r: r.arrival_s):
@@ -233,6 +239,8 @@ def serve_sequential_plain(requests: Sequence[W.Request], backend) -> List[Resul
         res.done = backend.now()
         res.mode = "plain"
         out.append(res)
+        if progress:
+            progress(len(out), len(requests))
     return out
 
 
@@ -260,14 +268,20 @@ def main(argv=None) -> None:
     ap.add_argument("--skip-plain", action="store_true")
     args = ap.parse_args(argv)
     from . import qsim
+
+    def progress(tag):
+        def f(done, total):
+            if done % 20 == 0 or done == total:
+                print(f"[serve] {tag}: {done}/{total} done", file=sys.stderr, flush=True)
+        return f
     reqs = W.serving_stream(args.requests, args.rate, args.seed, args.n_min, args.n_max)
     out = {"config": vars(args)}
     be = GpuBackend(qsim.OPT_ALL, n_streams=args.streams)
-    out["served"] = summarize(serve(reqs, be, max_streams=args.streams))
+    out["served"] = summarize(serve(reqs, be, max_streams=args.streams, progress=progress("served")))
     print(json.dumps({"served": out["served"]}), flush=True)
     if not args.skip_plain:
         bp = GpuBackend(0)
-        out["sequential_plain"] = summarize(serve_sequential_plain(reqs, bp))
+        out["sequential_plain"] = summarize(serve_sequential_plain(reqs, bp, progress=progress("plain")))
     print(json.dumps(out), flush=True)
 
 

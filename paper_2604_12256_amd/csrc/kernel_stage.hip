@@ -105,6 +105,16 @@ __device__ __forceinline__ uint32_t reg_offset(int j, const int *pos)
     return o;
 }
 
+template <int RB>
+__device__ __forceinline__ uint64_t reg_phys_offset(int j, const uint64_t *regphys)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+        if ((j >> b) & 1) o |= regphys[b];
+    return o;
+}
+
 // Dense operator on the register bits of MASK; m holds (2^k)^2 entries,
 // bit t of its index <-> t-th set bit of MASK.
 template <typename R, int RB, int MASK, typename MP>
@@ -210,21 +220,50 @@ __device__ __forceinline__ uint32_t thread_local_base(uint32_t tid, const QS_CON
     return lb;
 }
 
-// Moves the chunk between two register/thread mappings through LDS.
+// Byte offsets in the LDS buffer of the register part of a local index,
+// after the swizzle: off[j] = swz(register offset of j) * sizeof(amplitude).
+// The swizzle is linear over XOR, so the table grows one XOR per entry from
+// the offsets of the single register bits.
+template <typename R, int RB>
+__device__ __forceinline__ void reg_lds_offsets(uint32_t rmask, uint32_t *off)
+{
+    constexpr int NR = 1 << RB;
+    uint32_t e[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        e[b] = swz<R>(1u << __builtin_ctz(rmask)) * (uint32_t)sizeof(c2_t<R>);
+        rmask &= rmask - 1;
+    }
+    off[0] = 0;
+#pragma unroll
+    for (int j = 1; j < NR; ++j) off[j] = off[j & (j - 1)] ^ e[__builtin_ctz(j)];
+}
+
+// Moves the chunk between two register/thread mappings through LDS.  The
+// thread and register parts of a local index have disjoint bits, so
+// swz(lb | r) = swz(lb) ^ swz(r): a per-thread term and a wave-uniform one.
 template <typename R, int RB>
 __device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t old_lb, uint32_t old_r,
                                           uint32_t new_lb, uint32_t new_r)
 {
     constexpr int NR = 1 << RB;
-    int pos[RB];
+    using V = c2_t<R>;
+    char *const base = reinterpret_cast<char *>(lds);
+    uint32_t off[NR];
     __syncthreads();
-    reg_positions<RB>(old_r, pos);
+    reg_lds_offsets<R, RB>(old_r, off);
+    // (the empty asm keeps the per-thread term opaque, so that the compiler
+    // does not expand the swizzle again per element)
+    uint32_t wb = swz<R>(old_lb) * (uint32_t)sizeof(V);
+    asm volatile("" : "+v"(wb));
 #pragma unroll
-    for (int j = 0; j < NR; ++j) lds[swz<R>(old_lb | reg_offset<RB>(j, pos))] = amp[j];
+    for (int j = 0; j < NR; ++j) *reinterpret_cast<V *>(base + (wb ^ off[j])) = amp[j];
     __syncthreads();
-    reg_positions<RB>(new_r, pos);
+    reg_lds_offsets<R, RB>(new_r, off);
+    uint32_t rb = swz<R>(new_lb) * (uint32_t)sizeof(V);
+    asm volatile("" : "+v"(rb));
 #pragma unroll
-    for (int j = 0; j < NR; ++j) amp[j] = lds[swz<R>(new_lb | reg_offset<RB>(j, pos))];
+    for (int j = 0; j < NR; ++j) amp[j] = *reinterpret_cast<const V *>(base + (rb ^ off[j]));
 }
 
 template <typename R, int RB>
@@ -260,17 +299,11 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     V amp[NR];
     for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
         const uint64_t cbase = deposit(chunk, Gmask);
-        {
-            const uint64_t pb = cbase | tphys;
+        // chunk bits, thread bits and register bits are disjoint: each
+        // amplitude is a per-thread pointer plus a wave-uniform offset
+        V *const pt = state + (cbase | tphys);
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                uint64_t o = pb;
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-                    if ((j >> b) & 1) o |= regphys[b];
-                amp[j] = state[o];
-            }
-        }
+        for (int j = 0; j < NR; ++j) amp[j] = pt[reg_phys_offset<RB>(j, regphys)];
         // current mapping: register mask and thread-map words (workgroup-uniform)
         uint32_t cur_lb = tid, cur_r = neutral_r;
         uint32_t cur_t0 = neutral_t[0], cur_t1 = neutral_t[1], cur_t2 = neutral_t[2];
@@ -320,17 +353,8 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
         }
         if (cur_r != neutral_r || cur_t0 != neutral_t[0] || cur_t1 != neutral_t[1] || cur_t2 != neutral_t[2])
             transpose<R, RB>(amp, lds, cur_lb, cur_r, tid, neutral_r);
-        {
-            const uint64_t pb = cbase | tphys;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                uint64_t o = pb;
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-                    if ((j >> b) & 1) o |= regphys[b];
-                state[o] = amp[j];
-            }
-        }
+        for (int j = 0; j < NR; ++j) pt[reg_phys_offset<RB>(j, regphys)] = amp[j];
         __syncthreads();  // LDS reuse by the next chunk
     }
 }

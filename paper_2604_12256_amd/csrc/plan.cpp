@@ -396,6 +396,61 @@ struct Builder {
         emit(Z);
     }
 
+    // LDS bank order of a phase's lane bits.  The stage kernel's transposes
+    // write and read 16-byte (complex128) or 8-byte (complex64) slots at a
+    // swizzled local index whose low slot bits take local bit l to bit
+    // l mod M (M = 4 for complex128, 5 for complex64).  The lanes the LDS
+    // serves together then hit distinct banks when lane bits 0..M-1 sit on
+    // local bits of residues 0..M-1 in that order (this holds whether the
+    // LDS serves 8 or 16 lanes of a 16-byte access per cycle).  Reorders
+    // the lane bits (the first six thread-id bits) toward that pattern; a
+    // wave bit no gate of the phase uses may replace a lane bit, which never
+    // makes a wave-uniform selector lane-varying.
+    void order_lanes_for_lds(std::vector<int> &t, const std::vector<int> &uses) const
+    {
+        const int M = o.reg_bits == 4 ? 4 : 5;
+        const int nl = 6;
+        if ((int)t.size() < nl) return;
+        std::vector<int> L(t.begin(), t.begin() + nl), W(t.begin() + nl, t.end());
+        std::vector<int> head(M, -1);
+        std::vector<bool> placed(nl, false);
+        for (int want = 0; want < M; ++want)
+            for (int i = 0; i < nl; ++i)
+                if (!placed[i] && L[i] % M == want) {
+                    head[want] = i;
+                    placed[i] = true;
+                    break;
+                }
+        for (int want = 0; want < M; ++want) {
+            if (head[want] >= 0) continue;
+            int w = -1, x = -1;
+            for (int j = 0; j < (int)W.size() && w < 0; ++j)
+                if (W[j] % M == want && uses[W[j]] == 0) w = j;
+            for (int i = 0; i < nl; ++i)  // the most-used unplaced lane bit leaves
+                if (!placed[i] && (x < 0 || uses[L[i]] > uses[L[x]])) x = i;
+            if (w < 0 || x < 0) continue;
+            std::swap(L[x], W[w]);
+            head[want] = x;
+            placed[x] = true;
+        }
+        std::vector<int> out;
+        for (int want = 0; want < M; ++want) {
+            int i = head[want];
+            if (i < 0)  // residue unavailable: any unplaced lane bit holds the slot
+                for (int j = 0; j < nl; ++j)
+                    if (!placed[j]) {
+                        i = j;
+                        placed[j] = true;
+                        break;
+                    }
+            out.push_back(L[i]);
+        }
+        for (int i = 0; i < nl; ++i)
+            if (!placed[i]) out.push_back(L[i]);
+        out.insert(out.end(), W.begin(), W.end());
+        t.swap(out);
+    }
+
     // Register phases of one stage: gate block search with limit r on the
     // qubits each gate needs in registers, over the stage's gate list (the
     // same search as the stage partition, one level down the memory
@@ -459,6 +514,7 @@ struct Builder {
             for (int i = 0; i < C; ++i)
                 if (!((R >> i) & 1)) ph.tmap.push_back(i);
             std::stable_sort(ph.tmap.begin(), ph.tmap.end(), [&](int a, int b) { return uses[a] < uses[b]; });
+            order_lanes_for_lds(ph.tmap, uses);
             uint64_t lane_phys = 0;
             for (int i = 0; i < 6 && i < (int)ph.tmap.size(); ++i) lane_phys |= 1ull << st.local[ph.tmap[i]];
             std::vector<const Operator *> tg;

@@ -174,6 +174,11 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
             std::vector<int> sel;
             if (k.type == qs::KOp::DENSE) {
                 mask = k.reg_mask;
+                // the stage kernel applies dense operators on one or two
+                // register bits or on the whole register tile
+                const int kr = __builtin_popcount(mask);
+                if (mask >= (1u << reg_bits) || !(kr == 1 || kr == 2 || kr == reg_bits))
+                    throw std::runtime_error("encode_stage: unsupported register mask");
                 sel = k.sel;
                 tables.insert(tables.end(), k.table.begin(), k.table.end());
             } else {

@@ -116,11 +116,14 @@ __device__ __forceinline__ uint64_t reg_phys_offset(int j, const uint64_t *regph
 }
 
 // Dense operator on the register bits of MASK; m holds (2^k)^2 entries,
-// bit t of its index <-> t-th set bit of MASK.
+// bit t of its index <-> t-th set bit of MASK.  One- and two-bit operators
+// are applied in place with no register copies: every output first
+// accumulates all its terms except the real part of its diagonal
+// coefficient; then each output's last FMA reads its own input for the last
+// time and may take over that input's registers.
 template <typename R, int RB, int MASK, typename MP>
 __device__ __forceinline__ void apply_dense(c2_t<R> *amp, MP m)
 {
-    using V = c2_t<R>;
     constexpr int K = __builtin_popcount(MASK);
     constexpr int D = 1 << K;
     constexpr int NR = 1 << RB;
@@ -139,21 +142,50 @@ __device__ __forceinline__ void apply_dense(c2_t<R> *amp, MP m)
                 }
             idx[c] = x;
         }
-        V v[D];
+        if constexpr (K > 2) {
+            // whole-tile operator: copies are negligible beside its (2^k)^2
+            // products, and fewer values stay live
+            c2_t<R> v[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) v[c] = amp[idx[c]];
+            for (int c = 0; c < D; ++c) v[c] = amp[idx[c]];
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                c2_t<R> acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
+#pragma unroll
+                for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
+                amp[idx[r]] = acc;
+            }
+            continue;
+        }
+        R ar[D], ai[D];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            V acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
+            // diagonal coefficient's imaginary part first (starts the sums)
+            const R dim = ldc<R>(m, (uint64_t)(r * D + r)).y;
+            ar[r] = -dim * amp[idx[r]].y;
+            ai[r] = dim * amp[idx[r]].x;
 #pragma unroll
-            for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
-            amp[idx[r]] = acc;
+            for (int c = 0; c < D; ++c) {
+                if (c == r) continue;
+                const c2_t<R> w = ldc<R>(m, (uint64_t)(r * D + c));
+                ar[r] = fma(w.x, amp[idx[c]].x, ar[r]);
+                ar[r] = fma(-w.y, amp[idx[c]].y, ar[r]);
+                ai[r] = fma(w.x, amp[idx[c]].y, ai[r]);
+                ai[r] = fma(w.y, amp[idx[c]].x, ai[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            const R dre = ldc<R>(m, (uint64_t)(r * D + r)).x;
+            amp[idx[r]].x = fma(dre, amp[idx[r]].x, ar[r]);
+            amp[idx[r]].y = fma(dre, amp[idx[r]].y, ai[r]);
         }
     }
 }
 
 // Diagonal operator on the register bits of MASK: register j is multiplied by
-// t[bits of j under MASK].
+// t[bits of j under MASK] (in place: the two products that need the other
+// part are formed first, each final FMA is its input's last use).
 template <typename R, int RB, int MASK, typename MP>
 __device__ __forceinline__ void apply_diag(c2_t<R> *amp, MP t)
 {
@@ -167,7 +199,10 @@ __device__ __forceinline__ void apply_diag(c2_t<R> *amp, MP t)
                 if ((j >> b) & 1) idx |= 1 << bit;
                 ++bit;
             }
-        amp[j] = cmul(amp[j], ldc<R>(t, (uint64_t)idx));
+        const c2_t<R> w = ldc<R>(t, (uint64_t)idx);
+        const R pr = -w.y * amp[j].y, pi = w.y * amp[j].x;
+        amp[j].x = fma(w.x, amp[j].x, pr);
+        amp[j].y = fma(w.x, amp[j].y, pi);
     }
 }
 
@@ -177,6 +212,8 @@ __device__ __forceinline__ void dispatch_diag(uint32_t mask, c2_t<R> *amp, MP t)
     if constexpr (M < (1 << RB)) {
         if (mask == (uint32_t)M) apply_diag<R, RB, M, MP>(amp, t);
         else dispatch_diag<R, RB, M + 1, MP>(mask, amp, t);
+    } else {
+        __builtin_unreachable();  // every mask below 2^RB is handled above
     }
 }
 
@@ -204,8 +241,11 @@ __device__ __forceinline__ void dispatch_dense(uint32_t mask, c2_t<R> *amp, MP m
             case 18: apply_dense<R, RB, 18, MP>(amp, m); break;
             case 20: apply_dense<R, RB, 20, MP>(amp, m); break;
             case 24: apply_dense<R, RB, 24, MP>(amp, m); break;
-            default: break;
+            default: __builtin_unreachable();
             }
+        } else {
+            // the host encodes only the masks above (stage_dense_mask_ok)
+            __builtin_unreachable();
         }
         break;
     }

@@ -131,15 +131,38 @@ bool convert_gates(const sim_gate *gates, uint64_t ng, int n, std::vector<qs::Op
 }
 
 // Program words of one stage (layout documented in kernel_stage.hip).
-void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, std::vector<cplx> &tables)
+// amp_bytes: bytes of one table entry on the device (16 complex128, 8 complex64).
+void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::vector<uint32_t> &w,
+                  std::vector<cplx> &tables)
 {
     const int C = (int)st.local.size(), n = st.buffer_qubits;
+    const int NR = 1 << reg_bits;
+    const bool c64 = amp_bytes == 8;
+    const uint32_t amp_shift = c64 ? 3u : 4u;
+    if (st.phases.size() > 96) throw std::runtime_error("encode_stage: too many phases");
     const size_t base = w.size();
-    w.resize(base + 128, 0);
+    w.resize(base + qs::kStageHeaderWords, 0);
     uint64_t L = 0;
-    for (int q : st.local) L |= 1ull << q;
+    int local_of[64];
+    for (int q = 0; q < 64; ++q) local_of[q] = -1;
+    for (int i = 0; i < C; ++i) {
+        L |= 1ull << st.local[i];
+        local_of[st.local[i]] = i;
+    }
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1);
     const uint64_t G = all & ~L;
+    // swizzled LDS byte offsets of the register part of a local index
+    auto reg_offsets = [&](uint32_t rmask, uint32_t *dst) {
+        int pos[8], nb = 0;
+        for (int i = 0; i < C; ++i)
+            if ((rmask >> i) & 1) pos[nb++] = i;
+        for (int j = 0; j < NR; ++j) {
+            uint32_t r = 0;
+            for (int b = 0; b < nb; ++b)
+                if ((j >> b) & 1) r |= 1u << pos[b];
+            dst[j] = qs::stage_swizzle(r, c64) << amp_shift;
+        }
+    };
     w[base + 0] = (uint32_t)C;
     w[base + 1] = (uint32_t)n;
     w[base + 2] = (uint32_t)st.phases.size();
@@ -149,26 +172,38 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
     w[base + 6] = (uint32_t)G;
     w[base + 7] = (uint32_t)(G >> 32);
     for (int i = 0; i < C; ++i) w[base + 8 + i] = (uint32_t)st.local[i];
+    {
+        const uint32_t neutral_r = ((1u << C) - 1) & ~((1u << (C - reg_bits)) - 1);
+        reg_offsets(neutral_r, &w[base + 128]);
+    }
     for (size_t p = 0; p < st.phases.size(); ++p) {
         const qs::Phase &ph = st.phases[p];
         w[base + 32 + p] = (uint32_t)(w.size() - base);
         const size_t pb = w.size();
-        w.resize(pb + 16 + 16 * ph.ops.size(), 0);
+        w.resize(pb + qs::kStagePhaseWords + NR + 16 * ph.ops.size(), 0);
         uint32_t rmask = 0;
         for (int i : ph.reg) rmask |= 1u << i;
         const uint32_t nonr = ((1u << C) - 1) & ~rmask;
+        if ((int)ph.tmap.size() != C - reg_bits) throw std::runtime_error("encode_stage: bad thread map");
+        const int nwave = C - reg_bits - 6;
+        if (nwave < 0 || nwave > 8) throw std::runtime_error("encode_stage: bad thread count");
         w[pb + 0] = (uint32_t)ph.ops.size();
         w[pb + 1] = nonr;
         w[pb + 2] = rmask;
-        if ((int)ph.tmap.size() != C - reg_bits) throw std::runtime_error("encode_stage: bad thread map");
+        w[pb + 3] = (uint32_t)nwave;
         for (size_t i = 0; i < ph.tmap.size(); ++i) w[pb + 4 + i / 4] |= (uint32_t)ph.tmap[i] << (8 * (i % 4));
+        // physical bit of each wave bit of the thread id (thread-id bits 6, 7, ...)
+        for (int i = 0; i < nwave; ++i)
+            w[pb + 8 + i / 4] |= (uint32_t)st.local[ph.tmap[6 + i]] << (8 * (i % 4));
+        reg_offsets(rmask, &w[pb + qs::kStagePhaseWords]);
         std::vector<int> reg_phys;
         for (int i : ph.reg) reg_phys.push_back(st.local[i]);
-        uint64_t lane_phys = 0;
-        for (int i = 0; i < 6; ++i) lane_phys |= 1ull << st.local[ph.tmap[i]];
+        int tid_bit_of_local[64];
+        for (int i = 0; i < 64; ++i) tid_bit_of_local[i] = -1;
+        for (size_t i = 0; i < ph.tmap.size(); ++i) tid_bit_of_local[ph.tmap[i]] = (int)i;
         for (size_t o = 0; o < ph.ops.size(); ++o) {
             const qs::KOp &k = ph.ops[o];
-            uint32_t *op = &w[pb + 16 + 16 * o];
+            uint32_t *op = &w[pb + qs::kStagePhaseWords + NR + 16 * o];
             const uint64_t toff = tables.size();
             uint32_t mask = 0;
             std::vector<int> sel;
@@ -215,15 +250,30 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, std::vector<uint32_t> &w, 
                     }
                 tables.insert(tables.end(), tab.begin(), tab.end());
             }
-            if (sel.size() > 32) throw std::runtime_error("encode_stage: too many selector bits");
+            if (sel.size() > 28) throw std::runtime_error("encode_stage: too many selector bits");
+            // selector source bytes: a lane bit of the thread id (0x80 | bit), or
+            // the physical position of a chunk or wave bit (wave-uniform)
             bool uni = true;
-            for (int t : sel)
-                if ((lane_phys >> t) & 1) uni = false;
+            for (size_t t = 0; t < sel.size(); ++t) {
+                const int q = sel[t];
+                uint32_t code = (uint32_t)q;
+                if (local_of[q] >= 0) {
+                    const int tb = tid_bit_of_local[local_of[q]];
+                    if (tb < 0) throw std::runtime_error("encode_stage: selector on a register bit");
+                    if (tb < 6) {
+                        code = 0x80u | (uint32_t)tb;
+                        uni = false;
+                    }
+                }
+                op[3 + t / 4] |= code << (8 * (t % 4));
+            }
+            const int km = __builtin_popcount(mask);
+            const uint32_t shift = (k.type == qs::KOp::DENSE ? 2u * (uint32_t)km : (uint32_t)km) + amp_shift;
             op[0] = (k.type == qs::KOp::DENSE ? 1u : 2u) | (mask << 8) | ((uint32_t)sel.size() << 16) |
-                    ((uni ? 1u : 0u) << 24);
-            op[1] = (uint32_t)toff;
-            op[2] = (uint32_t)(toff >> 32);
-            for (size_t t = 0; t < sel.size(); ++t) op[3 + t / 4] |= (uint32_t)sel[t] << (8 * (t % 4));
+                    ((uni ? 1u : 0u) << 24) | (shift << 25);
+            const uint64_t tbytes = toff * amp_bytes;
+            op[1] = (uint32_t)tbytes;
+            op[2] = (uint32_t)(tbytes >> 32);
         }
     }
 }
@@ -347,7 +397,7 @@ sim_status prepare(sim_ctx *c)
                 p.C = (int)op.local.size();
                 p.nph = (int)op.phases.size();
                 p.nchunks = 1ull << (op.buffer_qubits - p.C);
-                encode_stage(op, c->opt.reg_bits, prog, tables);
+                encode_stage(op, c->opt.reg_bits, c->dtype == SIM_C64 ? 8u : 16u, prog, tables);
             }
             break;
         }

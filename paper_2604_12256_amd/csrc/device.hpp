@@ -126,6 +126,18 @@ template <typename R> hipError_t launch_small_ptrs(const SmallPtrs &P, uint32_t 
 int small_max_qubits(bool c128);
 
 // Stage kernel: program built by the executor (see kernel_stage.hip).
+// LDS slot swizzle of the stage kernel's transpose buffer (linear over XOR):
+// 16-byte slots (complex128) fold local-index bits 4..15 into bits 0..3,
+// 8-byte slots (complex64) fold bits 5..14 into bits 0..4, so that local bit
+// l lands on slot bit l mod 4 (resp. l mod 5).  The host writes the
+// swizzled byte offsets of each register set into the stage program.
+__host__ __device__ inline uint32_t stage_swizzle(uint32_t i, bool c64)
+{
+    return c64 ? i ^ (((i >> 5) ^ (i >> 10)) & 31u) : i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12)) & 15u);
+}
+constexpr int kStageHeaderWords = 160;   // program header incl. neutral offsets at [128, 128 + 2^RB)
+constexpr int kStagePhaseWords = 16;     // phase header before its register offsets
+
 struct StageLaunch {
     void *state;
     const uint32_t *prog;    // device program words

@@ -18,13 +18,19 @@
 // Program words (built on the host; read with wave-uniform loads):
 //   header  [0] C  [1] n  [2] nphases  [3] RB  [4,5] local mask  [6,7] global mask
 //           [8 + i] physical bit of local bit i (i < C)   [32 + p] word offset of phase p
+//           [128 + j] LDS byte offset of register j in the load/store mapping
 //   phase   [0] nops  [1] non-register local mask  [2] register local mask
+//           [3] number of wave bits of the thread id (thread-id bits 6, 7, ...)
 //           [4..7] local bit of thread-id bit i (bytes; bits 0..5 are the lane bits)
-//           [16 + 16 o ...] op o (a 64-byte record, loaded in one scalar load)
+//           [8, 9] physical bit of wave bit i (bytes)
+//           [16 + j] LDS byte offset of register j (swizzled; j < 2^RB)
+//           [16 + 2^RB + 16 o ...] op o (a 64-byte record)
 //   op      [0] type (bits 0-7: 1 dense, 2 diagonal) | register mask (bits of the
 //           register tile the operator acts on) << 8 | selector count << 16 |
-//           selectors wave-uniform << 24   [1,2] table offset
-//           [3..10] physical selector bit positions (bytes)
+//           selectors wave-uniform << 24 | log2 of the table bytes per selector value << 25
+//           [1,2] table byte offset   [3..9] selector sources (bytes): 0x80 | b is
+//           lane bit b of the thread id, any other value the physical position of
+//           a chunk or wave bit
 //   A dense op's table holds 2^nsel matrices of (2^k)^2 entries, a diagonal
 //   op's 2^nsel blocks of 2^k factors (k = popcount of the register mask).
 #include "device.hpp"
@@ -36,16 +42,9 @@ namespace {
 constexpr int kStageMaxThreads = 512;
 constexpr uint32_t kStageLdsBytes = 128u * 1024u;
 
-template <typename R> __device__ __forceinline__ uint32_t swz(uint32_t i);
-// 16-byte slots: fold the higher index bits into the low 4 (64 banks x 4 B).
-template <> __device__ __forceinline__ uint32_t swz<double>(uint32_t i)
+template <typename R> __device__ __forceinline__ uint32_t swz(uint32_t i)
 {
-    return i ^ (((i >> 4) ^ (i >> 8) ^ (i >> 12)) & 15u);
-}
-// 8-byte slots: fold into the low 5 bits.
-template <> __device__ __forceinline__ uint32_t swz<float>(uint32_t i)
-{
-    return i ^ (((i >> 5) ^ (i >> 10)) & 31u);
+    return stage_swizzle(i, sizeof(R) == 4);
 }
 
 __device__ __forceinline__ uint32_t byte_at(const QS_CONST uint32_t *w, int i)
@@ -65,44 +64,36 @@ __device__ __forceinline__ OpRec load_rec(const QS_CONST uint32_t *p)
     return r;
 }
 
-// Bits of `bits` at the selector positions of an op record (bit u of the
-// result = bit pos[u]).  Up to four selectors come from the record held in
-// scalar registers; wider diagonals read their positions from memory.
-template <typename B>
-__device__ __forceinline__ uint32_t gather_sel(const OpRec &r, const QS_CONST uint32_t *rec, uint32_t nsel, B bits)
+// Selector value of an op record: bit u from selector source byte u (a lane
+// bit of the thread id, or a bit of the wave-uniform base `ub`).  Up to four
+// sources come from the record held in scalar registers; wider diagonals
+// read theirs from memory.
+template <bool LANE>
+__device__ __forceinline__ uint32_t sel_bit(uint32_t b, uint64_t ub, uint32_t tid)
 {
-    uint32_t sel = 0;
+    if (LANE && (b & 0x80u)) return (tid >> (b & 63u)) & 1u;
+    return (uint32_t)(ub >> (b & 63u)) & 1u;
+}
+
+template <bool LANE>
+__device__ __forceinline__ uint32_t gather_sel(const OpRec &r, const QS_CONST uint32_t *rec, uint32_t nsel,
+                                               uint64_t ub, uint32_t tid)
+{
+    if (nsel == 0) return 0;
     if (nsel <= 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t pos = (r.w[3] >> (8 * u)) & 0xffu;
-            if ((uint32_t)u < nsel) sel |= (uint32_t)((bits >> pos) & 1ull) << u;
+        uint32_t sel = sel_bit<LANE>(r.w[3] & 0xffu, ub, tid);
+        if (nsel > 1) {
+            sel |= sel_bit<LANE>((r.w[3] >> 8) & 0xffu, ub, tid) << 1;
+            if (nsel > 2) {
+                sel |= sel_bit<LANE>((r.w[3] >> 16) & 0xffu, ub, tid) << 2;
+                if (nsel > 3) sel |= sel_bit<LANE>(r.w[3] >> 24, ub, tid) << 3;
+            }
         }
-    } else {
-        for (uint32_t u = 0; u < nsel; ++u)
-            sel |= (uint32_t)((bits >> byte_at(rec + 3, (int)u)) & 1ull) << u;
+        return sel;
     }
+    uint32_t sel = 0;
+    for (uint32_t u = 0; u < nsel; ++u) sel |= sel_bit<LANE>(byte_at(rec + 3, (int)u), ub, tid) << u;
     return sel;
-}
-
-template <int RB>
-__device__ __forceinline__ void reg_positions(uint32_t rmask, int *pos)
-{
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-        pos[b] = __builtin_ctz(rmask);
-        rmask &= rmask - 1;
-    }
-}
-
-template <int RB>
-__device__ __forceinline__ uint32_t reg_offset(int j, const int *pos)
-{
-    uint32_t o = 0;
-#pragma unroll
-    for (int b = 0; b < RB; ++b)
-        if ((j >> b) & 1) o |= 1u << pos[b];
-    return o;
 }
 
 template <int RB>
@@ -260,50 +251,30 @@ __device__ __forceinline__ uint32_t thread_local_base(uint32_t tid, const QS_CON
     return lb;
 }
 
-// Byte offsets in the LDS buffer of the register part of a local index,
-// after the swizzle: off[j] = swz(register offset of j) * sizeof(amplitude).
-// The swizzle is linear over XOR, so the table grows one XOR per entry from
-// the offsets of the single register bits.
-template <typename R, int RB>
-__device__ __forceinline__ void reg_lds_offsets(uint32_t rmask, uint32_t *off)
-{
-    constexpr int NR = 1 << RB;
-    uint32_t e[RB];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-        e[b] = swz<R>(1u << __builtin_ctz(rmask)) * (uint32_t)sizeof(c2_t<R>);
-        rmask &= rmask - 1;
-    }
-    off[0] = 0;
-#pragma unroll
-    for (int j = 1; j < NR; ++j) off[j] = off[j & (j - 1)] ^ e[__builtin_ctz(j)];
-}
-
 // Moves the chunk between two register/thread mappings through LDS.  The
-// thread and register parts of a local index have disjoint bits, so
-// swz(lb | r) = swz(lb) ^ swz(r): a per-thread term and a wave-uniform one.
+// thread and register parts of a local index have disjoint bits, so the
+// swizzled slot is swz(lb) ^ swz(r): a per-thread term and a wave-uniform
+// one, the latter read from the program (byte offsets of each register).
 template <typename R, int RB>
-__device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t old_lb, uint32_t old_r,
-                                          uint32_t new_lb, uint32_t new_r)
+__device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t old_lb,
+                                          const QS_CONST uint32_t *old_off, uint32_t new_lb,
+                                          const QS_CONST uint32_t *new_off)
 {
     constexpr int NR = 1 << RB;
     using V = c2_t<R>;
     char *const base = reinterpret_cast<char *>(lds);
-    uint32_t off[NR];
     __syncthreads();
-    reg_lds_offsets<R, RB>(old_r, off);
     // (the empty asm keeps the per-thread term opaque, so that the compiler
     // does not expand the swizzle again per element)
     uint32_t wb = swz<R>(old_lb) * (uint32_t)sizeof(V);
     asm volatile("" : "+v"(wb));
 #pragma unroll
-    for (int j = 0; j < NR; ++j) *reinterpret_cast<V *>(base + (wb ^ off[j])) = amp[j];
+    for (int j = 0; j < NR; ++j) *reinterpret_cast<V *>(base + (wb ^ old_off[j])) = amp[j];
     __syncthreads();
-    reg_lds_offsets<R, RB>(new_r, off);
     uint32_t rb = swz<R>(new_lb) * (uint32_t)sizeof(V);
     asm volatile("" : "+v"(rb));
 #pragma unroll
-    for (int j = 0; j < NR; ++j) amp[j] = *reinterpret_cast<const V *>(base + (rb ^ off[j]));
+    for (int j = 0; j < NR; ++j) amp[j] = *reinterpret_cast<const V *>(base + (rb ^ new_off[j]));
 }
 
 template <typename R, int RB>
@@ -314,8 +285,8 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
 {
     using V = c2_t<R>;
     const QS_CONST uint32_t *P = as_const(Pg);
-    const QS_CONST R *ctables = as_const(reinterpret_cast<const R *>(tables));
-    const R *rtables = reinterpret_cast<const R *>(tables);
+    const QS_CONST char *ctables = reinterpret_cast<const QS_CONST char *>(as_const(reinterpret_cast<const R *>(tables)));
+    const char *rtables = reinterpret_cast<const char *>(tables);
     constexpr int NR = 1 << RB;
     extern __shared__ char smem_raw[];
     V *lds = reinterpret_cast<V *>(smem_raw);
@@ -325,9 +296,11 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     const uint64_t Lmask = (uint64_t)P[4] | ((uint64_t)P[5] << 32);
     const uint64_t Gmask = (uint64_t)P[6] | ((uint64_t)P[7] << 32);
     const uint32_t tid = threadIdx.x;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid) >> 6;
     const uint32_t all_local = (1u << C) - 1;
     const uint32_t neutral_nonr = (1u << (C - RB)) - 1;
     const uint32_t neutral_r = all_local & ~neutral_nonr;
+    const QS_CONST uint32_t *const neutral_off = P + 128;
     uint64_t regphys[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) regphys[b] = 1ull << P[8 + C - RB + b];
@@ -347,52 +320,51 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
         // current mapping: register mask and thread-map words (workgroup-uniform)
         uint32_t cur_lb = tid, cur_r = neutral_r;
         uint32_t cur_t0 = neutral_t[0], cur_t1 = neutral_t[1], cur_t2 = neutral_t[2];
+        const QS_CONST uint32_t *cur_off = neutral_off;
         for (int p = 0; p < nph; ++p) {
             const QS_CONST uint32_t *ph = P + P[32 + p];
             const uint32_t nops = ph[0], rmask = ph[2];
             const uint32_t t0 = ph[4], t1 = ph[5], t2 = ph[6];
             if (rmask != cur_r || t0 != cur_t0 || t1 != cur_t1 || t2 != cur_t2) {
                 const uint32_t lb = thread_local_base(tid, ph + 4, C - RB);
-                transpose<R, RB>(amp, lds, cur_lb, cur_r, lb, rmask);
+                transpose<R, RB>(amp, lds, cur_lb, cur_off, lb, ph + 16);
                 cur_lb = lb;
                 cur_r = rmask;
                 cur_t0 = t0;
                 cur_t1 = t1;
                 cur_t2 = t2;
+                cur_off = ph + 16;
             }
-            const uint32_t lb = cur_lb;
-            const uint64_t phys_base = cbase | deposit(lb, Lmask);
-            // wave-uniform bits (wave part of the thread id and the chunk bits)
-            // taken from the first lane, for scalar selector extraction
-            const uint64_t pb_u = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(phys_base >> 32)) << 32) |
-                                  (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)phys_base);
-            const QS_CONST uint32_t *recs = ph + 16;
+            // wave-uniform base: chunk bits and the wave bits of the thread id
+            // at their physical positions
+            uint64_t ub = cbase;
+            const uint32_t nwave = ph[3];
+            for (uint32_t i = 0; i < nwave; ++i)
+                if ((wave >> i) & 1u) ub |= 1ull << byte_at(ph + 8, (int)i);
+            const QS_CONST uint32_t *recs = ph + 16 + NR;
             OpRec cur = load_rec(recs);
             for (uint32_t o = 0; o < nops; ++o) {
                 OpRec nxt;
                 if (o + 1 < nops) nxt = load_rec(recs + 16 * (o + 1));  // prefetch the next record
                 const uint32_t head = cur.w[0];
-                const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0xffu;
+                const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0xffu, shift = head >> 25;
                 const uint64_t toff = (uint64_t)cur.w[1] | ((uint64_t)cur.w[2] << 32);
-                const int k = __builtin_popcount(mask);
                 if ((head >> 24) & 1u) {  // selectors constant across the wave: scalar extraction and loads
-                    const uint32_t sel = gather_sel(cur, recs + 16 * o, nsel, pb_u);
-                    if ((head & 0xffu) == 1u)
-                        dispatch_dense<R, RB>(mask, amp, ctables + 2 * (toff + ((uint64_t)sel << (2 * k))));
-                    else
-                        dispatch_diag<R, RB>(mask, amp, ctables + 2 * (toff + ((uint64_t)sel << k)));
+                    const uint32_t sel = gather_sel<false>(cur, recs + 16 * o, nsel, ub, tid);
+                    const QS_CONST R *m = reinterpret_cast<const QS_CONST R *>(ctables + toff + ((uint64_t)sel << shift));
+                    if ((head & 0xffu) == 1u) dispatch_dense<R, RB>(mask, amp, m);
+                    else dispatch_diag<R, RB>(mask, amp, m);
                 } else {                  // selectors vary by lane: per-lane loads
-                    const uint32_t sel = gather_sel(cur, recs + 16 * o, nsel, phys_base);
-                    if ((head & 0xffu) == 1u)
-                        dispatch_dense<R, RB>(mask, amp, rtables + 2 * (toff + ((uint64_t)sel << (2 * k))));
-                    else
-                        dispatch_diag<R, RB>(mask, amp, rtables + 2 * (toff + ((uint64_t)sel << k)));
+                    const uint32_t sel = gather_sel<true>(cur, recs + 16 * o, nsel, ub, tid);
+                    const R *m = reinterpret_cast<const R *>(rtables + toff + ((uint64_t)sel << shift));
+                    if ((head & 0xffu) == 1u) dispatch_dense<R, RB>(mask, amp, m);
+                    else dispatch_diag<R, RB>(mask, amp, m);
                 }
                 cur = nxt;
             }
         }
         if (cur_r != neutral_r || cur_t0 != neutral_t[0] || cur_t1 != neutral_t[1] || cur_t2 != neutral_t[2])
-            transpose<R, RB>(amp, lds, cur_lb, cur_r, tid, neutral_r);
+            transpose<R, RB>(amp, lds, cur_lb, cur_off, tid, neutral_off);
 #pragma unroll
         for (int j = 0; j < NR; ++j) pt[reg_phys_offset<RB>(j, regphys)] = amp[j];
         __syncthreads();  // LDS reuse by the next chunk

@@ -242,12 +242,16 @@ __device__ __forceinline__ void dispatch_dense(uint32_t mask, c2_t<R> *amp, MP m
     }
 }
 
-// Local index of thread-id bits under a phase's thread map.
-__device__ __forceinline__ uint32_t thread_local_base(uint32_t tid, const QS_CONST uint32_t *tmap, int nbits)
+// Local index of thread-id bits under a phase's thread map (map bytes packed
+// in t0..t2: byte i = local bit of thread-id bit i), branch-free.
+__device__ __forceinline__ uint32_t thread_local_base(uint32_t tid, uint32_t t0, uint32_t t1, uint32_t t2,
+                                                      int nbits)
 {
+    const uint32_t t[3] = {t0, t1, t2};
     uint32_t lb = 0;
-    for (int i = 0; i < nbits; ++i)
-        if ((tid >> i) & 1) lb |= 1u << byte_at(tmap, i);
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+        if (i < nbits) lb |= ((tid >> i) & 1u) << ((t[i / 4] >> (8 * (i % 4))) & 0xffu);
     return lb;
 }
 
@@ -296,7 +300,11 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     const uint64_t Lmask = (uint64_t)P[4] | ((uint64_t)P[5] << 32);
     const uint64_t Gmask = (uint64_t)P[6] | ((uint64_t)P[7] << 32);
     const uint32_t tid = threadIdx.x;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid) >> 6;
+    // wave index in a scalar register (the asm keeps the compiler from
+    // turning the uniform bit tests below back into per-lane code)
+    uint32_t wave;
+    asm volatile("v_readfirstlane_b32 %0, %1" : "=s"(wave) : "v"(tid));
+    wave >>= 6;
     const uint32_t all_local = (1u << C) - 1;
     const uint32_t neutral_nonr = (1u << (C - RB)) - 1;
     const uint32_t neutral_r = all_local & ~neutral_nonr;
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
             const uint32_t nops = ph[0], rmask = ph[2];
             const uint32_t t0 = ph[4], t1 = ph[5], t2 = ph[6];
             if (rmask != cur_r || t0 != cur_t0 || t1 != cur_t1 || t2 != cur_t2) {
-                const uint32_t lb = thread_local_base(tid, ph + 4, C - RB);
+                const uint32_t lb = thread_local_base(tid, t0, t1, t2, C - RB);
                 transpose<R, RB>(amp, lds, cur_lb, cur_off, lb, ph + 16);
                 cur_lb = lb;
                 cur_r = rmask;
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
             uint64_t ub = cbase;
             const uint32_t nwave = ph[3];
             for (uint32_t i = 0; i < nwave; ++i)
-                if ((wave >> i) & 1u) ub |= 1ull << byte_at(ph + 8, (int)i);
+                ub |= (uint64_t)((wave >> i) & 1u) << byte_at(ph + 8, (int)i);
             const QS_CONST uint32_t *recs = ph + 16 + NR;
             OpRec cur = load_rec(recs);
             for (uint32_t o = 0; o < nops; ++o) {

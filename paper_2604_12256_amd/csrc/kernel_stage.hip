@@ -259,26 +259,42 @@ __device__ __forceinline__ uint32_t thread_local_base(uint32_t tid, uint32_t t0,
 // thread and register parts of a local index have disjoint bits, so the
 // swizzled slot is swz(lb) ^ swz(r): a per-thread term and a wave-uniform
 // one, the latter read from the program (byte offsets of each register).
+typedef __attribute__((address_space(3))) char lds_byte_t;
+
 template <typename R, int RB>
-__device__ __forceinline__ void transpose(c2_t<R> *amp, c2_t<R> *lds, uint32_t old_lb,
+__device__ __forceinline__ void transpose(c2_t<R> *amp, uint32_t lds_base, uint32_t old_lb,
                                           const QS_CONST uint32_t *old_off, uint32_t new_lb,
                                           const QS_CONST uint32_t *new_off)
 {
     constexpr int NR = 1 << RB;
     using V = c2_t<R>;
-    char *const base = reinterpret_cast<char *>(lds);
+    struct alignas(2 * sizeof(R)) pair_t {
+        R x, y;
+    };
+    typedef __attribute__((address_space(3))) pair_t lds_v_t;
     __syncthreads();
-    // (the empty asm keeps the per-thread term opaque, so that the compiler
-    // does not expand the swizzle again per element)
-    uint32_t wb = swz<R>(old_lb) * (uint32_t)sizeof(V);
+    // LDS byte address = (base | per-thread term) ^ wave-uniform term; the
+    // base of the dynamic LDS is 0 here (the kernel has no static LDS), so
+    // OR and XOR do not carry into it.  (The empty asm keeps the per-thread
+    // term opaque, so that the compiler does not expand the swizzle again
+    // per element.)
+    uint32_t wb = lds_base | (swz<R>(old_lb) * (uint32_t)sizeof(V));
     asm volatile("" : "+v"(wb));
 #pragma unroll
-    for (int j = 0; j < NR; ++j) *reinterpret_cast<V *>(base + (wb ^ old_off[j])) = amp[j];
+    for (int j = 0; j < NR; ++j) {
+        lds_v_t *p = reinterpret_cast<lds_v_t *>((uintptr_t)(wb ^ old_off[j]));
+        p->x = amp[j].x;
+        p->y = amp[j].y;
+    }
     __syncthreads();
-    uint32_t rb = swz<R>(new_lb) * (uint32_t)sizeof(V);
+    uint32_t rb = lds_base | (swz<R>(new_lb) * (uint32_t)sizeof(V));
     asm volatile("" : "+v"(rb));
 #pragma unroll
-    for (int j = 0; j < NR; ++j) amp[j] = *reinterpret_cast<const V *>(base + (rb ^ new_off[j]));
+    for (int j = 0; j < NR; ++j) {
+        const lds_v_t *p = reinterpret_cast<const lds_v_t *>((uintptr_t)(rb ^ new_off[j]));
+        amp[j].x = p->x;
+        amp[j].y = p->y;
+    }
 }
 
 template <typename R, int RB>
@@ -293,7 +309,7 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     const char *rtables = reinterpret_cast<const char *>(tables);
     constexpr int NR = 1 << RB;
     extern __shared__ char smem_raw[];
-    V *lds = reinterpret_cast<V *>(smem_raw);
+    const uint32_t lds = (uint32_t)(uintptr_t)(lds_byte_t *)smem_raw;  // LDS byte address of the buffer
 
     const int C = (int)P[0];
     const int nph = (int)P[2];
@@ -350,25 +366,29 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
             for (uint32_t i = 0; i < nwave; ++i)
                 ub |= (uint64_t)((wave >> i) & 1u) << byte_at(ph + 8, (int)i);
             const QS_CONST uint32_t *recs = ph + 16 + NR;
-            OpRec cur = load_rec(recs);
-            for (uint32_t o = 0; o < nops; ++o) {
-                OpRec nxt;
-                if (o + 1 < nops) nxt = load_rec(recs + 16 * (o + 1));  // prefetch the next record
-                const uint32_t head = cur.w[0];
+            auto apply_op = [&](const OpRec &rec, uint32_t o) __attribute__((always_inline)) {
+                const uint32_t head = rec.w[0];
                 const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0xffu, shift = head >> 25;
-                const uint64_t toff = (uint64_t)cur.w[1] | ((uint64_t)cur.w[2] << 32);
-                if ((head >> 24) & 1u) {  // selectors constant across the wave: scalar extraction and loads
-                    const uint32_t sel = gather_sel<false>(cur, recs + 16 * o, nsel, ub, tid);
+                const uint64_t toff = (uint64_t)rec.w[1] | ((uint64_t)rec.w[2] << 32);
+                if ((head >> 24) & 1u) {
+                    const uint32_t sel = gather_sel<false>(rec, recs + 16 * o, nsel, ub, tid);
                     const QS_CONST R *m = reinterpret_cast<const QS_CONST R *>(ctables + toff + ((uint64_t)sel << shift));
                     if ((head & 0xffu) == 1u) dispatch_dense<R, RB>(mask, amp, m);
                     else dispatch_diag<R, RB>(mask, amp, m);
-                } else {                  // selectors vary by lane: per-lane loads
-                    const uint32_t sel = gather_sel<true>(cur, recs + 16 * o, nsel, ub, tid);
+                } else {
+                    const uint32_t sel = gather_sel<true>(rec, recs + 16 * o, nsel, ub, tid);
                     const R *m = reinterpret_cast<const R *>(rtables + toff + ((uint64_t)sel << shift));
                     if ((head & 0xffu) == 1u) dispatch_dense<R, RB>(mask, amp, m);
                     else dispatch_diag<R, RB>(mask, amp, m);
                 }
-                cur = nxt;
+            };
+            OpRec cur = load_rec(recs);
+            for (uint32_t o = 0; o < nops; o += 2) {
+                OpRec second;
+                if (o + 1 < nops) second = load_rec(recs + 16 * (o + 1));
+                apply_op(cur, o);
+                if (o + 2 < nops) cur = load_rec(recs + 16 * (o + 2));
+                if (o + 1 < nops) apply_op(second, o + 1);
             }
         }
         if (cur_r != neutral_r || cur_t0 != neutral_t[0] || cur_t1 != neutral_t[1] || cur_t2 != neutral_t[2])

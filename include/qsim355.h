@@ -218,6 +218,10 @@ typedef struct {
     uint32_t nq;
     uint32_t qubits[16];
     uint64_t payload_len;
+    uint32_t n_register;    /* stage-kernel operators: how many of the qubits the
+                               kernel holds in registers; the others select a
+                               block of the operator (0 in stage gate lists) */
+    uint32_t reserved;
 } sim_plan_gate;
 
 sim_status sim_plan_build(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts,

@@ -982,6 +982,9 @@ sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64
         if (k.type == qs::KOp::DIAG) {
             g->diagonal = 1;
             g->nq = (uint32_t)k.dq.size();
+            for (int q : k.dq)
+                for (int b : ph.reg)
+                    if (o.local[b] == q) g->n_register++;
             for (size_t t = 0; t < k.dq.size() && t < 16; ++t) g->qubits[t] = (uint32_t)k.dq[t];
             g->payload_len = k.table.size();
             if (payload)
@@ -998,6 +1001,7 @@ sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64
         for (int t : k.sel) q.push_back(t);
         g->diagonal = 0;
         g->nq = (uint32_t)q.size();
+        g->n_register = (uint32_t)kr;
         for (size_t t = 0; t < q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)q[t];
         const uint64_t D = 1ull << (kr + ks), dr = 1ull << kr;
         g->payload_len = D * D;

@@ -66,7 +66,7 @@ class SimPlanOp(ctypes.Structure):
 
 class SimPlanGate(ctypes.Structure):
     _fields_ = [("diagonal", ctypes.c_uint32), ("nq", ctypes.c_uint32), ("qubits", ctypes.c_uint32 * 16),
-                ("payload_len", ctypes.c_uint64)]
+                ("payload_len", ctypes.c_uint64), ("n_register", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class QsimError(RuntimeError):
@@ -328,7 +328,8 @@ class Plan:
                     mat = pl[:g.payload_len].copy()
                     if not g.diagonal:
                         mat = mat.reshape(1 << g.nq, 1 << g.nq)
-                    kops.append({"diagonal": bool(g.diagonal), "qubits": qs, "payload": mat})
+                    kops.append({"diagonal": bool(g.diagonal), "qubits": qs, "payload": mat,
+                                 "n_register": g.n_register})
                     j += 1
                 d["kernel_ops"] = kops
             elif d["kind"] == "PERM":

@@ -79,6 +79,29 @@ def test_stage_kernel_chunk_sizes(oracle_mod, C):
     check128(got, oracle_mod.run(n, gates), f"C={C}")
 
 
+def test_stage_kernel_operator_paths(oracle_mod):
+    """Rare stage-kernel paths against the oracle: diagonal tables with more
+    than four selector bits, two-bit dense operators with selectors, whole-
+    register-tile dense operators (the shapes are asserted on the CPU in
+    test_planner_cpu), in both precisions and several chunk sizes."""
+    from tests.test_planner_cpu import operator_path_circuit
+    n = 16
+    gates = operator_path_circuit(n, 3)
+    want = oracle_mod.run(n, gates)
+    opt = qsim.OPT_STAGES | qsim.OPT_FUSE | qsim.OPT_DIAG
+    for C in (11, 12, 13):
+        say(f"operator paths c128 C={C}")
+        got, _ = gpu_state(n, gates, opt=opt, C=C)
+        check128(got, want, f"c128 C={C}")
+    for C in (12, 13, 14):
+        say(f"operator paths c64 C={C}")
+        got, _ = gpu_state(n, gates, dtype="c64", opt=opt, C=C)
+        check64(got, want, oracle_mod, f"c64 C={C}")
+    say("operator paths all passes")
+    got, _ = gpu_state(n, gates, opt=qsim.OPT_ALL)
+    check128(got, want, "all passes")
+
+
 def test_layered_and_diag_heavy_all_opts(oracle_mod):
     for n, gates in ((18, W.layered(18, 10, 5)), (18, W.diag_heavy(18, 300, 6)), (20, W.layered(20, 5, 7))):
         want = oracle_mod.run(n, gates)

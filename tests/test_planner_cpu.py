@@ -298,3 +298,51 @@ def test_remap_free_relabel_at_start():
     assert p.layout() != list(range(n))
     q = qsim.Plan(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE)
     assert p.stats()["full_passes"] < q.stats()["full_passes"]
+
+
+def operator_path_circuit(n, seed):
+    """Circuit whose stages need the stage kernel's rarer operator shapes: a
+    fused nine-qubit diagonal (more than four selector bits), three- and four-qubit
+    dense gates (whole register tile) and controlled gates on many qubits
+    (block-diagonal operators with selectors)."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for layer in range(3):
+        for q in range(n):
+            gates.append(Gate("U", (q,), data=W.haar_unitary(rng)))
+        # two overlapping six-qubit diagonals and a phase gate: the diagonal
+        # detector fuses them into one wide table
+        qs = [int(x) for x in rng.choice(n, 9, replace=False)]
+        for part in (qs[:6], qs[3:]):
+            gates.append(Gate("DIAG", tuple(part), data=np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << 6))))
+        gates.append(Gate("CPHASE", (qs[0], qs[8]), theta=float(rng.uniform(0, 2 * np.pi))))
+        for k in (3, 4):
+            qk = tuple(int(x) for x in rng.choice(n, k, replace=False))
+            gates.append(Gate("U", qk, data=W.haar_unitary(rng, 1 << k)))
+        for _ in range(n):
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            gates.append(Gate("CNOT", (a, b)))
+            gates.append(Gate("CPHASE", (b, a), theta=float(rng.uniform(0, 2 * np.pi))))
+    return gates
+
+
+def test_operator_path_circuit_has_the_rare_shapes():
+    """The circuit used by the GPU operator-path test produces stage-kernel
+    operators with more than four selector bits (diagonal tables whose
+    selector sources are read from memory), two-bit dense operators with
+    selectors, and whole-register-tile dense operators."""
+    n = 16
+    opt = qsim.OPT_STAGES | qsim.OPT_FUSE | qsim.OPT_DIAG
+    ops = qsim.Plan(n, operator_path_circuit(n, 3), opt=opt, C=12).ops()
+    wide_sel = two_bit_sel = whole_tile = 0
+    for o in ops:
+        if o["kind"] != "STAGE":
+            continue
+        for k in o["kernel_ops"]:
+            nsel = len(k["qubits"]) - k["n_register"]
+            if k["diagonal"]:
+                wide_sel += nsel > 4
+            else:
+                two_bit_sel += k["n_register"] == 2 and nsel > 0
+                whole_tile += k["n_register"] == 4
+    assert wide_sel > 0 and two_bit_sel > 0 and whole_tile > 0, (wide_sel, two_bit_sel, whole_tile)

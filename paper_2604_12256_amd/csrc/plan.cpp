@@ -577,6 +577,70 @@ struct Builder {
         *Lout = L;
     }
 
+    // The greedy frontier with a fixed local set L: a gate is taken when none
+    // of its qubits is blocked, the qubits it needs are in L and fit the
+    // register tile; otherwise all its qubits become blocked.  Counts the
+    // gates taken (stopping once every qubit in `live` is blocked) or collects
+    // them; `wanted` gathers the global qubits whose absence turned a gate
+    // away that was not blocked otherwise.
+    size_t frontier(const Masks &M, const std::vector<int> &rem, uint64_t L, int r, uint64_t live,
+                    std::vector<int> *take, std::vector<int> *left, uint64_t *wanted = nullptr) const
+    {
+        uint64_t blocked = 0;
+        size_t n = 0;
+        for (size_t i = 0; i < rem.size(); ++i) {
+            const int gi = rem[i];
+            const uint64_t qs = M.qs[gi], nd = M.nd[gi];
+            if ((qs & blocked) || (nd & ~L) || popc(nd) > r) {
+                if (wanted && !(qs & blocked) && popc(nd) <= r) *wanted |= nd & ~L;
+                blocked |= qs;
+                if (left) left->push_back(gi);
+                if (!left && (blocked & live) == live) break;
+                continue;
+            }
+            ++n;
+            if (take) take->push_back(gi);
+        }
+        return n;
+    }
+
+    // Local search on a stage's local set (the gate block search chooses the
+    // local qubits in gate order; the choice decides how far the stage gets):
+    // swap one local qubit above the always-local low bits for a global qubit
+    // that a turned-away gate wanted, whenever the frontier then takes more
+    // gates, until no swap helps (at most kMaxEvals frontier evaluations).
+    uint64_t refine_local(const Masks &M, const std::vector<int> &rem, uint64_t L, int low, int r, int nb) const
+    {
+        constexpr int kMaxEvals = 300;
+        uint64_t live = 0;
+        for (int gi : rem) live |= M.qs[gi];
+        uint64_t wanted = 0;
+        size_t best = frontier(M, rem, L, r, live, nullptr, nullptr, &wanted);
+        int evals = 1;
+        bool improved = true;
+        while (improved && evals < kMaxEvals) {
+            improved = false;
+            for (int a = low; a < nb && !improved && evals < kMaxEvals; ++a) {
+                if (!((L >> a) & 1)) continue;
+                for (int b = low; b < nb && evals < kMaxEvals; ++b) {
+                    if (((L >> b) & 1) || !((wanted >> b) & 1)) continue;
+                    const uint64_t L2 = (L & ~(1ull << a)) | (1ull << b);
+                    uint64_t w2 = 0;
+                    const size_t c = frontier(M, rem, L2, r, live, nullptr, nullptr, &w2);
+                    ++evals;
+                    if (c > best) {
+                        best = c;
+                        L = L2;
+                        wanted = w2;
+                        improved = true;
+                        break;
+                    }
+                }
+            }
+        }
+        return L;
+    }
+
     // Gates consumed by the next `horizon` greedy stages.
     size_t lookahead(const Masks &M, std::vector<int> rem, int C, int low, int r, int horizon) const
     {
@@ -704,6 +768,12 @@ struct Builder {
             std::vector<int> take, left;
             greedy_stage(M, rem, C, low, r, &L, &take, &left);
             for (int q = 0; q < nb && popc(L) < C; ++q) L |= 1ull << q;
+            if (nb > C) {
+                L = refine_local(M, rem, L, low, r, nb);
+                take.clear();
+                left.clear();
+                frontier(M, rem, L, r, ~0ull, &take, &left);
+            }
             PlanOp st;
             st.kind = SIM_OP_STAGE;
             st.buffer = buffer;

@@ -301,8 +301,8 @@ def test_remap_free_relabel_at_start():
 
 
 def operator_path_circuit(n, seed):
-    """Circuit whose stages need the stage kernel's rarer operator shapes: a
-    fused nine-qubit diagonal (more than four selector bits), three- and four-qubit
+    """Circuit whose stages need the stage kernel's rarer operator shapes:
+    six-qubit diagonals (more than four selector bits), three- and four-qubit
     dense gates (whole register tile) and controlled gates on many qubits
     (block-diagonal operators with selectors)."""
     rng = np.random.default_rng(seed)
@@ -310,12 +310,12 @@ def operator_path_circuit(n, seed):
     for layer in range(3):
         for q in range(n):
             gates.append(Gate("U", (q,), data=W.haar_unitary(rng)))
-        # two overlapping six-qubit diagonals and a phase gate: the diagonal
-        # detector fuses them into one wide table
-        qs = [int(x) for x in rng.choice(n, 9, replace=False)]
-        for part in (qs[:6], qs[3:]):
-            gates.append(Gate("DIAG", tuple(part), data=np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << 6))))
-        gates.append(Gate("CPHASE", (qs[0], qs[8]), theta=float(rng.uniform(0, 2 * np.pi))))
+        # six-qubit diagonals, mostly on high qubits (global or thread bits of
+        # a stage, so most of their qubits select blocks), and a phase gate
+        for _ in range(3):
+            qs = [int(x) for x in rng.choice(np.arange(n // 4, n), 6, replace=False)]
+            gates.append(Gate("DIAG", tuple(qs), data=np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << 6))))
+        gates.append(Gate("CPHASE", (qs[0], qs[5]), theta=float(rng.uniform(0, 2 * np.pi))))
         for k in (3, 4):
             qk = tuple(int(x) for x in rng.choice(n, k, replace=False))
             gates.append(Gate("U", qk, data=W.haar_unitary(rng, 1 << k)))

@@ -711,9 +711,11 @@ struct Builder {
                 fresh = it->kind == SIM_OP_INIT;
                 break;
             }
-        // stages saved over the horizon ~ kHorizon * (1 - c0 / c1); a pass costs one
+        // stages saved over the horizon ~ kHorizon * (1 - c0 / c1); the in-place
+        // permutation pass costs about three stage passes on MI355X (measured:
+        // 18.9 ms against 6.8 ms for a plain 16 GiB copy pass)
         const double saved = c1 > 0 ? kHorizon * (1.0 - double(c0) / double(c1)) : 0.0;
-        if (!(c1 > c0 && (fresh || saved >= 1.5))) return false;
+        if (!(c1 > c0 && (fresh || saved >= 3.0))) return false;
         M.qs.swap(T.qs);
         M.nd.swap(T.nd);
         for (int gi : rem) swap_qubits(pg[gi], sigma);

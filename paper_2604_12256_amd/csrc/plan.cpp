@@ -19,28 +19,28 @@ namespace {
 
 int popc(uint64_t x) { return __builtin_popcountll(x); }
 
-// Cost model of one stage-kernel operator, in FMA-equivalents per amplitude
-// divided by the fraction of FP64 peak the operator reaches on MI355X
-// (measured per operator type at 30 qubits: a dense operator on 1 register
-// bit ~0.5, on 2 bits ~0.6, on the full 4-bit register tile ~0.28; a
-// diagonal one complex multiply per amplitude).
-double op_cost(bool diag, int dense_qubits)
+// Cost model of one stage-kernel operator: device microseconds per 2^30
+// amplitudes, measured on MI355X as the increment per operator inside
+// compute-bound stages (chunk 2^12 complex128 / 2^13 complex64).  Dense
+// operators on three or more register bits run as the whole register tile
+// (4 bits complex128, 5 bits complex64).
+double op_cost(bool diag, int dense_qubits, bool c64)
 {
-    if (diag) return 4.0 / 0.4;
-    static const double eff[] = {1.0, 0.5, 0.6, 0.4, 0.28, 0.3};
-    return 4.0 * double(1 << dense_qubits) / eff[dense_qubits < 5 ? dense_qubits : 5];
+    if (diag) return c64 ? 145.0 : 265.0;
+    if (dense_qubits <= 1) return c64 ? 247.0 : 286.0;
+    if (dense_qubits == 2) return c64 ? 478.0 : 652.0;
+    return c64 ? 9510.0 : 7570.0;
 }
 
-// Device seconds of one stage-kernel operator on 2^30 complex128
-// amplitudes, from microbenchmarks of the stage kernel on MI355X (about 1/27
-// microsecond per op_cost unit); complex64 halves the arithmetic.
+// Device seconds of one stage-kernel operator on `amps` amplitudes (diagonal
+// tables with more than four selector bits read their selector sources from
+// memory).
 double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64)
 {
-    const double scale = amps / 1073741824.0 * (c64 ? 0.5 : 1.0);
-    const double unit = 27e-6;
-    if (k.type == KOp::DIAG) return scale * unit * (op_cost(true, 0) + (k.dq.size() > 2 ? 3.0 : 0.0));
+    const double scale = amps / 1073741824.0 * 1e-6;
+    if (k.type == KOp::DIAG) return scale * (op_cost(true, 0, c64) + (k.dq.size() > 4 ? 80.0 : 0.0));
     const int kr = __builtin_popcount(k.reg_mask);
-    return scale * unit * op_cost(false, kr >= 3 ? reg_bits : kr);
+    return scale * op_cost(false, kr >= 3 ? reg_bits : kr, c64);
 }
 // Floating-point operations per amplitude: a dense k-qubit operator does 2^k
 // complex multiply-adds (8 flops each), a diagonal one complex multiply (6).
@@ -214,7 +214,8 @@ struct Builder {
         const bool fuse = (o.opt & SIM_OPT_FUSE) != 0;  // without it every gate is its own kernel op
         const uint32_t full = (1u << r) - 1;
         auto kernel_mask = [&](uint32_t S) { return popc(S) >= 3 ? full : S; };
-        auto dense_cost = [&](uint32_t S) { return op_cost(false, popc(kernel_mask(S))); };
+        const bool c64 = plan.dtype == SIM_C64;
+        auto dense_cost = [&](uint32_t S) { return op_cost(false, popc(kernel_mask(S)), c64); };
         auto lane_sel = [&](const std::vector<int> &T) {
             for (int t : T)
                 if ((lane_phys >> t) & 1) return true;
@@ -290,7 +291,7 @@ struct Builder {
                 Z.S = 0;
                 Z.T = T2;
                 Z.acc = embed(g, T2);
-                Z.indiv = op_cost(true, 0);
+                Z.indiv = op_cost(true, 0, c64);
                 return;
             }
             if (T2 != Z.acc.q) Z.acc = embed(Z.acc, T2);
@@ -330,7 +331,7 @@ struct Builder {
                 push_diag(g.q, g.m);
                 continue;
             }
-            const double gcost = g.diag ? op_cost(true, 0) : dense_cost(gS);
+            const double gcost = g.diag ? op_cost(true, 0, c64) : dense_cost(gS);
             // blocks owning a register qubit of g
             std::vector<size_t> own;
             for (size_t i = 0; i < open.size(); ++i)
@@ -342,7 +343,7 @@ struct Builder {
                 for (int x : gT)
                     if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
                 const bool diag2 = B.acc.diag && g.diag;
-                const double fused = diag2 ? op_cost(true, 0) : dense_cost(S2);
+                const double fused = diag2 ? op_cost(true, 0, c64) : dense_cost(S2);
                 const bool sel_ok = diag2 ? (int)T2.size() <= kTmaxUniform
                                           : (lane_sel(T2) ? ((int)T2.size() <= kTmaxLane && popc(kernel_mask(S2)) <= 2)
                                                           : (int)T2.size() <= kTmaxUniform);
@@ -872,13 +873,21 @@ struct Builder {
         }
     }
 
-    // Estimated device time of an op (cost model of the adaptive simulator):
-    // the larger of its HBM time and its arithmetic time at sustained rates,
-    // plus a launch overhead.
+    // Estimated device time of an op (cost model of the adaptive simulator).
+    // A stage: HBM time at the measured copy rate (5.1 TB/s) and compute time
+    // (its operators plus a fixed per-chunk part: loads, stores, transposes)
+    // overlap, the smaller contributing a fifth (measured on MI355X).  Full
+    // passes: the larger of HBM and arithmetic time.  Plus a launch overhead.
     static double est_seconds(const PlanOp &op)
     {
-        if (op.kind == SIM_OP_STAGE) return op.bytes / 5.5e12 + op.est_s + 4e-6;
-        return std::max(op.bytes / 5.5e12, op.flops / 55e12) + 4e-6;
+        if (op.kind == SIM_OP_STAGE) {
+            const double amps = std::ldexp(1.0, op.buffer_qubits);
+            const bool c64 = op.bytes < 24.0 * amps;  // 2 x 8 B per amplitude
+            const double mem = op.bytes / 5.1e12;
+            const double comp = op.est_s + (c64 ? 1.5e-3 : 2.5e-3) * amps / 1073741824.0;
+            return std::max(mem, comp) + 0.2 * std::min(mem, comp) + 4e-6;
+        }
+        return std::max(op.bytes / 5.1e12, op.flops / 55e12) + 4e-6;
     }
 
     // Executes the gates of one buffer with the enabled passes.  With cache

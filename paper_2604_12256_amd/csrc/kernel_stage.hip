@@ -65,9 +65,9 @@ __device__ __forceinline__ OpRec load_rec(const QS_CONST uint32_t *p)
 }
 
 // Selector value of an op record: bit u from selector source byte u (a lane
-// bit of the thread id, or a bit of the wave-uniform base `ub`).  Up to four
-// sources come from the record held in scalar registers; wider diagonals
-// read theirs from memory.
+// bit of the thread id, or a bit of the wave-uniform base `ub`).  Up to
+// twelve sources come from the record held in scalar registers; wider
+// diagonals read theirs from memory.
 template <bool LANE>
 __device__ __forceinline__ uint32_t sel_bit(uint32_t b, uint64_t ub, uint32_t tid)
 {
@@ -92,6 +92,12 @@ __device__ __forceinline__ uint32_t gather_sel(const OpRec &r, const QS_CONST ui
         return sel;
     }
     uint32_t sel = 0;
+    if (nsel <= 12) {  // sources in record words 3..5, loaded with the record
+#pragma unroll
+        for (uint32_t u = 0; u < 12; ++u)
+            if (u < nsel) sel |= sel_bit<LANE>((r.w[3 + u / 4] >> (8 * (u % 4))) & 0xffu, ub, tid) << u;
+        return sel;
+    }
     for (uint32_t u = 0; u < nsel; ++u) sel |= sel_bit<LANE>(byte_at(rec + 3, (int)u), ub, tid) << u;
     return sel;
 }

@@ -32,13 +32,15 @@ double op_cost(bool diag, int dense_qubits, bool c64)
     return c64 ? 9510.0 : 7570.0;
 }
 
-// Device seconds of one stage-kernel operator on `amps` amplitudes (diagonal
-// tables with more than four selector bits read their selector sources from
-// memory).
+// Device seconds of one stage-kernel operator on `amps` amplitudes.  Wide
+// diagonals (more than four qubits, from the diagonal detector) mostly have
+// selector bits on lanes, where every lane loads its own table entries:
+// about 200 microseconds more per 2^30 amplitudes (measured on the 30-qubit
+// diagonal-heavy circuit).
 double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64)
 {
     const double scale = amps / 1073741824.0 * 1e-6;
-    if (k.type == KOp::DIAG) return scale * (op_cost(true, 0, c64) + (k.dq.size() > 4 ? 80.0 : 0.0));
+    if (k.type == KOp::DIAG) return scale * (op_cost(true, 0, c64) + (k.dq.size() > 4 ? (c64 ? 110.0 : 200.0) : 0.0));
     const int kr = __builtin_popcount(k.reg_mask);
     return scale * op_cost(false, kr >= 3 ? reg_bits : kr, c64);
 }

@@ -612,13 +612,36 @@ struct Builder {
     // swap one local qubit above the always-local low bits for a global qubit
     // that a turned-away gate wanted, whenever the frontier then takes more
     // gates, until no swap helps (at most kMaxEvals frontier evaluations).
+    // Frontier count on a contiguous copy of the remaining gates' masks.
+    static size_t frontier_count(const std::vector<uint64_t> &qs, const std::vector<uint64_t> &nd, uint64_t L,
+                                 int r, uint64_t live, uint64_t *wanted)
+    {
+        uint64_t blocked = 0;
+        size_t n = 0;
+        for (size_t i = 0; i < qs.size(); ++i) {
+            if ((qs[i] & blocked) || (nd[i] & ~L) || popc(nd[i]) > r) {
+                if (!(qs[i] & blocked) && popc(nd[i]) <= r) *wanted |= nd[i] & ~L;
+                blocked |= qs[i];
+                if ((blocked & live) == live) break;
+                continue;
+            }
+            ++n;
+        }
+        return n;
+    }
+
     uint64_t refine_local(const Masks &M, const std::vector<int> &rem, uint64_t L, int low, int r, int nb) const
     {
         constexpr int kMaxEvals = 300;
+        std::vector<uint64_t> qs(rem.size()), nd(rem.size());
         uint64_t live = 0;
-        for (int gi : rem) live |= M.qs[gi];
+        for (size_t i = 0; i < rem.size(); ++i) {
+            qs[i] = M.qs[rem[i]];
+            nd[i] = M.nd[rem[i]];
+            live |= qs[i];
+        }
         uint64_t wanted = 0;
-        size_t best = frontier(M, rem, L, r, live, nullptr, nullptr, &wanted);
+        size_t best = frontier_count(qs, nd, L, r, live, &wanted);
         int evals = 1;
         bool improved = true;
         while (improved && evals < kMaxEvals) {
@@ -629,7 +652,7 @@ struct Builder {
                     if (((L >> b) & 1) || !((wanted >> b) & 1)) continue;
                     const uint64_t L2 = (L & ~(1ull << a)) | (1ull << b);
                     uint64_t w2 = 0;
-                    const size_t c = frontier(M, rem, L2, r, live, nullptr, nullptr, &w2);
+                    const size_t c = frontier_count(qs, nd, L2, r, live, &w2);
                     ++evals;
                     if (c > best) {
                         best = c;

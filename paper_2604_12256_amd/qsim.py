@@ -147,6 +147,18 @@ class _Gates:
         self.arr = arr
 
 
+class Circuit(_Gates):
+    """A circuit already marshalled into the ABI's gate array: `load` it any
+    number of times without converting the Python gates again."""
+
+    def __init__(self, gates: Sequence) -> None:
+        super().__init__(gates)
+
+
+def _as_gates(gates) -> _Gates:
+    return gates if isinstance(gates, _Gates) else _Gates(gates)
+
+
 def _options(opt: int, C: int, F: int, D: int, B: int, force_fuse_k: int, state_ptr: int = 0,
              state_bytes: int = 0, stream: int = 0) -> SimOptions:
     o = SimOptions()
@@ -186,8 +198,9 @@ class Simulator:
         if st != OK:
             raise QsimError(st, self._lib.sim_last_error(self._ctx).decode())
 
-    def load(self, gates: Sequence) -> None:
-        m = _Gates(gates)
+    def load(self, gates) -> None:
+        """Validates and plans a circuit: a sequence of gates or a `Circuit`."""
+        m = _as_gates(gates)
         self._check(self._lib.sim_load_circuit(self._ctx, m.arr, m.n))
         self.n_gates = m.n
 
@@ -278,7 +291,7 @@ class Plan:
                  F: int = 0, D: int = 0, B: int = 0, force_fuse_k: int = 0) -> None:
         self._lib = load_library()
         self.n = n
-        m = _Gates(gates)
+        m = _as_gates(gates)
         o = _options(opt, C, F, D, B, force_fuse_k)
         p = ctypes.c_void_p()
         st = self._lib.sim_plan_build(n, DTYPES[dtype], ctypes.byref(o), m.arr, m.n, ctypes.byref(p))

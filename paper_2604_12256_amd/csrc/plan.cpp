@@ -411,7 +411,7 @@ struct Builder {
     // makes a wave-uniform selector lane-varying.
     void order_lanes_for_lds(std::vector<int> &t, const std::vector<int> &uses) const
     {
-        const int M = o.reg_bits == 4 ? 4 : 5;
+        const int M = plan.dtype == SIM_C128 ? 4 : 5;  // slot bits of the swizzle: 16-byte or 8-byte slots
         const int nl = 6;
         if ((int)t.size() < nl) return;
         std::vector<int> L(t.begin(), t.begin() + nl), W(t.begin() + nl, t.end());

@@ -346,3 +346,29 @@ def test_operator_path_circuit_has_the_rare_shapes():
                 two_bit_sel += k["n_register"] == 2 and nsel > 0
                 whole_tile += k["n_register"] == 4
     assert wide_sel > 0 and two_bit_sel > 0 and whole_tile > 0, (wide_sel, two_bit_sel, whole_tile)
+
+
+def test_stage_partition_quality_layered30():
+    """Regression guard for the stage partition: the 30-qubit layered circuit
+    (2,680 gates) plans into at most 22 full-state passes with all passes on
+    (the gate block search alone, taking local qubits in gate order, needs 30)."""
+    n, gates = W.config_circuit("layered30")
+    st = qsim.Plan(n, gates).stats()
+    assert st["full_passes"] <= 22, st
+    assert st["n_perm"] == 0
+
+
+def test_premarshalled_circuit_plans_identically():
+    """A `Circuit` (gates converted once) plans exactly like the gate list."""
+    n, gates = 14, W.layered(14, 8, seed=3)
+    a = qsim.Plan(n, gates).ops()
+    circ = qsim.Circuit(gates)
+    for _ in range(2):  # reusable
+        b = qsim.Plan(n, circ).ops()
+        assert [o["kind"] for o in a] == [o["kind"] for o in b]
+        for x, y in zip(a, b):
+            if x["kind"] == "STAGE":
+                assert x["local"] == y["local"]
+                assert len(x["kernel_ops"]) == len(y["kernel_ops"])
+                for kx, ky in zip(x["kernel_ops"], y["kernel_ops"]):
+                    assert np.array_equal(kx["payload"], ky["payload"])

@@ -423,8 +423,12 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
         if (e != hipSuccess) return e;
         attr_set = true;
     }
+    // at most 2^15 workgroups: on large states each walks several chunks, so
+    // its set-up (thread bases, mapping tables) is paid once per several
+    // chunks (measured best on MI355X against one chunk per workgroup and
+    // against fewer, longer-lived workgroups)
     uint64_t grid = L.nchunks;
-    if (grid > (1ull << 20)) grid = 1ull << 20;
+    if (grid > (1ull << 15)) grid = 1ull << 15;
     k_stage<R, RB><<<(uint32_t)grid, threads, lds, s>>>((c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables,
                                                         L.nchunks);
     return hipGetLastError();

@@ -156,6 +156,100 @@ def cpu_baseline(name, n_prefix):
                       f"incl. |0> init), {dt:.1f} s"}
 
 
+def kernel_table(n=30):
+    """Per-kernel device time and HBM rate at `n` qubits (both dtypes), each
+    kernel driven through the C ABI: full-pass dense gates on the VALU
+    (k = 1..3) and on MFMA (k = 4, 5), full-pass diagonals, the tensor
+    product of the merge booster, |0...0>, the output reductions (marginal,
+    inner product, amplitude gather) and the batched small-state kernel.
+    Rates are algorithmic bytes (one read and one write of the state for a
+    pass) over the measured time."""
+    import numpy as np
+    import torch
+    from paper_2604_12256_amd import qsim
+    from paper_2604_12256_amd import workloads as W
+    from paper_2604_12256_amd.workloads import Gate
+    rng = np.random.default_rng(11)
+    rows = []
+
+    def events(fn, reps=3):
+        best = 1e9
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    for dtype in ("c128", "c64"):
+        b = 16 if dtype == "c128" else 8
+        state_bytes = b << n
+        a = torch.empty((2 if dtype == "c128" else 1) << n, dtype=torch.float64, device="cuda")
+        other = torch.empty_like(a)
+
+        def op_ms(gates, opt, kind):
+            sim = qsim.Simulator(n, dtype=dtype, opt=opt, state=a)
+            sim.set_profiling(True)
+            sim.load(gates)
+            best = 1e9
+            for _ in range(3):
+                sim.run()
+                best = min(best, sum(t["ms"] for t in sim.op_timings() if t["kind"] == kind and t["buffer"] == 0))
+            sim.close()
+            return best
+
+        def add(kernel, what, ms, nbytes):
+            rows.append({"dtype": dtype, "kernel": kernel, "op": what, "ms": round(ms, 3),
+                         "GBps": round(nbytes / ms / 1e6, 1), "hbm_frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 3)})
+            log(f"[kernels] {dtype} {kernel} {what}: {ms:.3f} ms")
+
+        add("k_init", "|0...0>", op_ms([], 0, "INIT"), state_bytes)
+        for k in (1, 2, 3):
+            g = [Gate("U", tuple(range(7, 7 + k)), data=W.haar_unitary(rng, 1 << k))]
+            add("k_dense", f"dense k={k} (qubits 7..)", op_ms(g, 0, "DENSE"), 2 * state_bytes)
+        for k in (4, 5):
+            g = [Gate("U", tuple(range(7, 7 + k)), data=W.haar_unitary(rng, 1 << k))]
+            add("k_dense_mfma", f"dense k={k} (qubits 7..)", op_ms(g, 0, "DENSE"), 2 * state_bytes)
+        for k in (1, 6):
+            g = [Gate("DIAG", tuple(range(20, 20 + k)), data=np.exp(1j * rng.uniform(0, 6.3, 1 << k)))]
+            add("k_diag", f"diagonal k={k} (qubits 20..)", op_ms(g, 0, "DIAG"), 2 * state_bytes)
+        add("k_kron", "tensor product of two 15-qubit sub-states",
+            op_ms(W.product_circuit(n, 2, 5), qsim.OPT_BOOST | qsim.OPT_STAGES, "KRON"), state_bytes)
+        sim = qsim.Simulator(n, dtype=dtype, opt=0, state=a)
+        sim.load([Gate("H", (q,)) for q in range(3)])
+        sim.run()
+        add("k_marg_partial_lanes", "marginal over qubits 0..9",
+            events(lambda: sim.probabilities(list(range(10)))), state_bytes)
+        add("k_marg_partial", "marginal over qubits 20..29",
+            events(lambda: sim.probabilities(list(range(20, 30)))), state_bytes)
+        sim2 = qsim.Simulator(n, dtype=dtype, opt=0, state=other)
+        sim2.load([Gate("H", (q,)) for q in range(2)])
+        sim2.run()
+        add("k_inner_*", "inner product of two states", events(lambda: sim.inner(sim2)), 2 * state_bytes)
+        idx = np.sort(rng.choice(1 << n, 1 << 20, replace=False)).astype(np.uint64)
+        add("k_gather", "2^20 sampled amplitudes incl. host index upload and copy-out",
+            events(lambda: sim.amplitudes(idx)), (1 << 20) * b)
+        sim.close()
+        sim2.close()
+        del a, other
+        torch.cuda.empty_cache()
+        # batched small circuits: 128 circuits of 12 qubits, 20 layers each
+        sims = []
+        for i in range(128):
+            s_ = qsim.Simulator(12, dtype=dtype, opt=qsim.OPT_ALL)
+            s_.load(W.layered(12, 20, seed=100 + i))
+            sims.append(s_)
+        ms = events(lambda: qsim.run_batch(sims))
+        rows.append({"dtype": dtype, "kernel": "k_small_ptrs", "op": "128 circuits x 12 qubits x 540 gates, one launch",
+                     "ms": round(ms, 3), "gate_apps_per_s": round(128 * 540 / (ms / 1e3), 1)})
+        log(f"[kernels] {dtype} k_small_ptrs: {ms:.3f} ms")
+        for s_ in sims:
+            s_.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,12 +260,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-prefix", type=int, default=60)
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--kernels", action="store_true",
+                    help="print a per-kernel time / HBM-rate table at 30 qubits instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the state vector is not sharded across "
               "GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     from paper_2604_12256_amd import qsim
+    if args.kernels:
+        print(json.dumps({"kernels": kernel_table()}), flush=True)
+        return
     log(f"[bench] workload {args.workload} {args.dtype} steps={args.steps} warmup={args.warmup}")
     r = run_workload(args.workload, args.dtype, qsim.OPT_ALL, args.steps, args.warmup)
     ms_per_step = r["wall_s"] / args.steps * 1e3

@@ -728,7 +728,7 @@ sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, do
     std::vector<int> sorted = ph;
     std::sort(sorted.begin(), sorted.end());
     const size_t nbins = 1ull << nq;
-    const size_t scr = qs::marginal_scratch_bytes(c->n, (int)nq);
+    const size_t scr = qs::marginal_scratch_bytes(c->n, sorted.data(), (int)nq);
     HIPCHK(c, grow(c->scratch, scr + nbins * 8 + 64), "scratch allocation");
     double *dout = (double *)((char *)c->scratch.p + ((scr + 63) / 64) * 64);
     hipError_t e = c->dtype == SIM_C128

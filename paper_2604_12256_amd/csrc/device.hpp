@@ -115,7 +115,7 @@ template <typename R> hipError_t launch_gather(const void *state, const uint64_t
 // marginal over the physical qubits q[0..nq): out[2^nq] doubles (device), scratch as sized by marginal_scratch_bytes
 template <typename R> hipError_t launch_marginal(const void *state, int n, const int *q, int nq, double *out,
                                                  double *scratch, hipStream_t s);
-size_t marginal_scratch_bytes(int n, int nq);
+size_t marginal_scratch_bytes(int n, const int *q, int nq);  // q ascending, as passed to launch_marginal
 template <typename RA, typename RB> hipError_t launch_inner(const void *a, const void *b, int n, double *out,
                                                             double *scratch, hipStream_t s);
 size_t inner_scratch_bytes(int n);

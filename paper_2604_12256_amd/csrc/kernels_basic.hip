@@ -284,6 +284,59 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const c2_t<R> *__restri
     if (lane == 0) part[seg * nbins + y] = acc;
 }
 
+// Marginal over a qubit set that includes some of the low six qubits: each
+// wave reads contiguous runs of 64 amplitudes (lane = low six address bits),
+// so every lane accumulates the bin its lane bits select.  Wave w takes one
+// value yh of the selected high qubits and a segment of the unselected high
+// bits; afterwards the lanes of a bin (differing only in unselected low bits)
+// are combined by a fixed butterfly.  Bin bit order: ascending qubits (the
+// selected low qubits first, then yh).
+struct MargLaneArgs {
+    uint32_t sl;            // selected low qubits (mask over bits 0..5)
+    int32_t kl, kh;         // counts of selected low / high qubits
+    int32_t shi[24];        // selected high qubits, ascending
+    uint64_t zseg;          // unselected-high values per segment
+    uint32_t nseg;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_marg_partial_lanes(const c2_t<R> *__restrict__ a, MargLaneArgs M,
+                                                               double *__restrict__ part)
+{
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nyh = 1ull << M.kh;
+    if (wave >= nyh * M.nseg) return;  // whole waves (the wave index is uniform)
+    const uint64_t yh = wave % nyh, seg = wave / nyh;
+    uint64_t base = 0;
+    for (int t = 0; t < M.kh; ++t) base |= ((yh >> t) & 1ull) << M.shi[t];
+    double acc = 0.0;
+    const uint64_t z0 = seg * M.zseg;
+#pragma unroll 4
+    for (uint64_t z = z0; z < z0 + M.zseg; ++z) {
+        // z over the unselected high bits: zeros inserted at the selected
+        // high qubits (wave-uniform)
+        uint64_t hz = z;
+        for (int t = 0; t < M.kh; ++t) {
+            const int p = M.shi[t] - 6;
+            hz = ((hz >> p) << (p + 1)) | (hz & ((1ull << p) - 1));
+        }
+        const c2_t<R> v = a[base | (hz << 6) | lane];
+        const double re = (double)v.x, im = (double)v.y;
+        acc += re * re + im * im;
+    }
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if (!((M.sl >> b) & 1u)) acc += __shfl_xor(acc, 1 << b, 64);
+    if ((lane & ~M.sl & 63u) == 0) {
+        uint32_t yl = 0;
+        for (int b = 0, t = 0; b < 6; ++b)
+            if ((M.sl >> b) & 1u) yl |= ((lane >> b) & 1u) << t++;
+        const uint64_t bin = (uint64_t)yl | (yh << M.kl);
+        part[seg * (1ull << (M.kl + M.kh)) + bin] = acc;
+    }
+}
+
 // Few bins, many segments: one block per bin, fixed strided sums then a
 // fixed tree.
 __global__ __launch_bounds__(kBlock) void k_marg_final_block(const double *__restrict__ part, uint64_t nbins,
@@ -469,11 +522,33 @@ void marg_shape(int n, int nq, uint64_t *zseg, uint32_t *nseg)
 }
 }  // namespace
 
-size_t marginal_scratch_bytes(int n, int nq)
+// Segments of the lane-contiguous marginal: enough waves to fill the chip
+// (2^15), each sweeping at least 64 runs.
+void marg_lane_shape(int n, int kh, uint64_t *zseg, uint32_t *nseg)
+{
+    const uint64_t nz = 1ull << (n - 6 - kh);
+    uint64_t seg = 1;
+    while ((seg << kh) < (1ull << 15) && nz / (seg * 2) >= 64) seg *= 2;
+    *nseg = (uint32_t)seg;
+    *zseg = nz / seg;
+}
+
+bool marg_by_lanes(int n, const int *q, int nq)
+{
+    return n >= 8 && nq > 0 && q[0] < 6 && (n - 6) > 0;
+}
+
+size_t marginal_scratch_bytes(int n, const int *q, int nq)
 {
     uint64_t zseg;
     uint32_t nseg;
-    marg_shape(n, nq, &zseg, &nseg);
+    if (marg_by_lanes(n, q, nq)) {
+        int kh = 0;
+        for (int t = 0; t < nq; ++t) kh += q[t] >= 6;
+        marg_lane_shape(n, kh, &zseg, &nseg);
+    } else {
+        marg_shape(n, nq, &zseg, &nseg);
+    }
     return (size_t)nseg * (1ull << nq) * sizeof(double);
 }
 
@@ -492,14 +567,32 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
     // y bit t <-> qubit q[t]: deposit() fills ascending positions, so the
     // bins come out in ascending-qubit order; the executor passes q sorted and
     // reorders on the host.
-    marg_shape(n, nq, &M.zseg, &M.nseg);
     const uint64_t nbins = 1ull << nq;
-    const uint64_t waves = nbins * M.nseg;
-    k_marg_partial<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, M, scratch);
-    if (nbins < kBlock && M.nseg >= 64)
-        k_marg_final_block<<<(uint32_t)nbins, kBlock, 0, s>>>(scratch, nbins, M.nseg, out);
+    uint32_t nseg;
+    if (marg_by_lanes(n, q, nq)) {  // low qubits selected: lane-contiguous reads
+        MargLaneArgs L{};
+        for (int t = 0; t < nq; ++t) {
+            if (q[t] < 6) {
+                L.sl |= 1u << q[t];
+                ++L.kl;
+            } else {
+                L.shi[L.kh++] = q[t];
+            }
+        }
+        marg_lane_shape(n, L.kh, &L.zseg, &L.nseg);
+        nseg = L.nseg;
+        const uint64_t waves = (1ull << L.kh) * L.nseg;
+        k_marg_partial_lanes<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, L, scratch);
+    } else {
+        marg_shape(n, nq, &M.zseg, &M.nseg);
+        nseg = M.nseg;
+        const uint64_t waves = nbins * M.nseg;
+        k_marg_partial<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, M, scratch);
+    }
+    if (nseg >= 64)
+        k_marg_final_block<<<(uint32_t)nbins, kBlock, 0, s>>>(scratch, nbins, nseg, out);
     else
-        k_marg_final<<<blocks_for(nbins, kBlock), kBlock, 0, s>>>(scratch, nbins, M.nseg, out);
+        k_marg_final<<<blocks_for(nbins, kBlock), kBlock, 0, s>>>(scratch, nbins, nseg, out);
     return hipGetLastError();
 }
 

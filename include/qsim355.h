@@ -79,7 +79,9 @@ enum {
     SIM_OPT_FUSE = 1u << 1,    /* cost-based gate fusion up to F qubits */
     SIM_OPT_STAGES = 1u << 2,  /* cache blocking: chunk-resident stages (Alg. 2, Alg. 5) */
     SIM_OPT_BOOST = 1u << 3,   /* merge booster (Sec. 4.4, Alg. 6-7) */
-    SIM_OPT_REMAP = 1u << 4,   /* qubit reordering between stages (Sec. 2.3), needs STAGES */
+    SIM_OPT_REMAP = 1u << 4,   /* qubit reordering (Sec. 2.3): permutation passes between
+                                  stages (needs STAGES), and SWAP gates (an exact 0/1 exchange
+                                  matrix) become relabellings that move no data */
     SIM_OPT_ALL = 0x1Fu
 };
 

@@ -76,6 +76,10 @@ struct sim_ctx {
     std::vector<qs::Operator> gates;
     qs::Plan plan;
     bool loaded = false, ran = false;
+    // logical -> physical qubit map of the state the last run produced: the
+    // plan's layout after sim_run, the identity after a batched small-state
+    // run (which applies the input gates in logical order)
+    std::vector<int> layout;
 
     DevBuf tables, prog, gdesc, items, scratch, io;
     std::vector<DevBuf> subbufs;          // booster sub-states (index = buffer id)
@@ -651,6 +655,7 @@ sim_status sim_run_async(sim_ctx *c)
     HIPCHK(c, hipEventRecord(c->ev1, c->stream), "event record");
     c->timing_pending = true;
     c->ran = true;
+    c->layout = c->plan.layout;
     return SIM_OK;
 }
 
@@ -672,7 +677,7 @@ sim_status sim_amplitudes(sim_ctx *c, const uint64_t *idx, uint64_t m, double *o
     if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
     if (!out && m) return fail(c, SIM_E_INVAL, "out is NULL");
     const uint64_t len = 1ull << c->n;
-    const std::vector<int> &lay = c->plan.layout;
+    const std::vector<int> &lay = c->layout;
     bool identity = true;
     for (int q = 0; q < c->n; ++q) identity &= (lay[q] == q);
     auto phys = [&](uint64_t x) {
@@ -723,7 +728,7 @@ sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, do
         if ((int)qubits[t] >= c->n) return fail(c, SIM_E_INVAL, "qubit out of range");
         for (uint32_t u = 0; u < t; ++u)
             if (qubits[u] == qubits[t]) return fail(c, SIM_E_INVAL, "duplicate qubit");
-        ph[t] = c->plan.layout[qubits[t]];
+        ph[t] = c->layout[qubits[t]];
     }
     std::vector<int> sorted = ph;
     std::sort(sorted.begin(), sorted.end());
@@ -759,11 +764,11 @@ sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out)
     if (a->n != b->n) return fail(a, SIM_E_INVAL, "qubit counts differ");
     if (!a->ran || !b->ran) return fail(a, SIM_E_STATE, "both contexts must have run");
     HIPCHK(a, hipStreamSynchronize(b->stream), "synchronize");
-    if (a->plan.layout != b->plan.layout) {
+    if (a->layout != b->layout) {
         // element i of a (physical) is logical x = pa^-1(i); b holds it at pb(x)
         std::vector<int> inv_a(a->n), map(a->n);
-        for (int q = 0; q < a->n; ++q) inv_a[a->plan.layout[q]] = q;
-        for (int p = 0; p < a->n; ++p) map[p] = b->plan.layout[inv_a[p]];
+        for (int q = 0; q < a->n; ++q) inv_a[a->layout[q]] = q;
+        for (int p = 0; p < a->n; ++p) map[p] = b->layout[inv_a[p]];
         const size_t scr = qs::inner_scratch_bytes(a->n);
         HIPCHK(a, grow(a->scratch, scr + 64), "scratch allocation");
         double *dout = (double *)((char *)a->scratch.p + scr);
@@ -883,6 +888,8 @@ sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream)
     for (uint32_t i = 0; i < n_ctx; ++i) {
         ctxs[i]->ran = true;
         ctxs[i]->timing_pending = false;
+        ctxs[i]->layout.resize(ctxs[i]->n);
+        for (int q = 0; q < ctxs[i]->n; ++q) ctxs[i]->layout[q] = q;
     }
     return SIM_OK;
 }

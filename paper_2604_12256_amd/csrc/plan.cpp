@@ -1091,6 +1091,43 @@ struct Builder {
 
 }  // namespace
 
+namespace {
+
+// True for the exact two-qubit exchange |ab> -> |ba> (entries exactly 0 and 1).
+bool is_swap(const Operator &g)
+{
+    if (g.k() != 2 || g.diag) return false;
+    for (uint64_t r = 0; r < 4; ++r)
+        for (uint64_t c = 0; c < 4; ++c) {
+            const uint64_t sr = ((r & 1) << 1) | (r >> 1);
+            if (g.at(r, c) != cplx(c == sr ? 1.0 : 0.0, 0.0)) return false;
+        }
+    return true;
+}
+
+// Qubit relabelling (Sec. 2.3: a swap only changes which index bit holds a
+// qubit, so the gates after it are re-indexed): with remapping enabled a SWAP
+// gate moves no data.  pi[q] is the label logical qubit q carries after the
+// swaps seen so far; later gates act on the relabelled qubits.
+std::vector<Operator> relabel_swaps(const std::vector<Operator> &gates, int n, std::vector<int> &pi)
+{
+    pi.resize(n);
+    for (int q = 0; q < n; ++q) pi[q] = q;
+    std::vector<Operator> out;
+    out.reserve(gates.size());
+    for (const Operator &g : gates) {
+        if (is_swap(g)) {
+            std::swap(pi[g.q[0]], pi[g.q[1]]);
+            continue;
+        }
+        out.push_back(g);
+        for (int &q : out.back().q) q = pi[q];
+    }
+    return out;
+}
+
+}  // namespace
+
 void build_plan(Plan &plan, const std::vector<Operator> &gates)
 {
     auto t0 = std::chrono::steady_clock::now();
@@ -1099,15 +1136,26 @@ void build_plan(Plan &plan, const std::vector<Operator> &gates)
     plan.buffer_qubits.assign(1, plan.n);
     plan.layout.resize(plan.n);
     for (int q = 0; q < plan.n; ++q) plan.layout[q] = q;
+    std::vector<int> pi;
+    const bool relabel = (plan.opt.opt & SIM_OPT_REMAP) &&
+                         std::any_of(gates.begin(), gates.end(), [](const Operator &g) { return is_swap(g); });
+    std::vector<Operator> relabelled;
+    if (relabel) relabelled = relabel_swaps(gates, plan.n, pi);
+    const std::vector<Operator> &in = relabel ? relabelled : gates;
     Builder b{plan, plan.opt};
     std::vector<Operator> rest;
     if (plan.opt.opt & SIM_OPT_BOOST) {
-        rest = b.booster(gates);
+        rest = b.booster(in);
     } else {
         b.init_op(0, plan.n);
-        rest = gates;
+        rest = in;
     }
     b.lower(0, plan.n, std::move(rest));
+    if (relabel) {  // logical q carries label pi[q], which sits at bit layout[pi[q]]
+        std::vector<int> lay(plan.n);
+        for (int q = 0; q < plan.n; ++q) lay[q] = plan.layout[pi[q]];
+        plan.layout.swap(lay);
+    }
     plan.stats.n_ops = plan.ops.size();
     for (const PlanOp &op : plan.ops)
         if (op.buffer == 0) plan.stats.est_ms += 1e3 * Builder::est_seconds(op);

@@ -23,6 +23,17 @@ Workload recipes (all numpy PCG64 via ``numpy.random.default_rng``):
   {RZ, CZ, CPHASE, RZZ} and 20 % non-diagonal gates from {H, SX, U},
   interleaved by a seeded shuffle; qubits uniform (pairs distinct), angles
   ~ U[0, 2 pi).
+* ``rzz_full``: H on every qubit, then RZZ(theta) on every pair i < j
+  (i outer, j inner), theta ~ U[0, 2 pi): the gate-level benchmark of
+  Sec. 5.2 (Table 1).
+* ``qft``: X on the set bits of a seeded basis index x0, then the textbook
+  quantum Fourier transform (H and controlled phases from the top qubit
+  down, then the qubit-order reversal by SWAPs): the circuit-level QFT of
+  Sec. 5.3.
+* ``qaoa_full``: H on every qubit, then per level RZZ(gamma_l) on every pair
+  i < j and RX(beta_l) on every qubit, gamma_l and beta_l ~ U[0, pi): the
+  5-level fully-connected QAOA of Sec. 5.3 and the ablation of Table 3
+  (unweighted complete graph).
 * ``serving_stream``: Poisson arrivals of layered circuits with N uniform in
   {10..30}, depth uniform in [10, 60] and a fair coin between complex128 and
   complex64.
@@ -176,6 +187,59 @@ def random_mixed(n: int, n_gates: int, seed: int, max_k: int = 3,
     return gates
 
 
+def rzz_full(n: int, seed: int = 7) -> List[Gate]:
+    """H on every qubit, then RZZ on all n(n-1)/2 pairs with seeded angles."""
+    rng = np.random.default_rng(seed)
+    gates = [Gate("H", (q,)) for q in range(n)]
+    for i in range(n):
+        for j in range(i + 1, n):
+            gates.append(Gate("RZZ", (i, j), float(rng.uniform(0.0, 2.0 * math.pi))))
+    return gates
+
+
+def qft_input_index(n: int, seed: int) -> int:
+    """The seeded basis index x0 that ``qft`` prepares before the transform."""
+    rng = np.random.default_rng(seed)
+    return int(rng.integers(0, 1 << n, dtype=np.uint64))
+
+
+def qft(n: int, seed: int = 8) -> List[Gate]:
+    """X gates preparing |x0> (x0 = qft_input_index(n, seed)), then the QFT:
+    for j = n-1 down to 0, H on j and CPHASE(pi / 2^(j-k)) on (k, j) for
+    k = j-1 down to 0; finally SWAP(j, n-1-j) for j < n/2."""
+    x0 = qft_input_index(n, seed)
+    gates = [Gate("X", (q,)) for q in range(n) if (x0 >> q) & 1]
+    for j in range(n - 1, -1, -1):
+        gates.append(Gate("H", (j,)))
+        for k in range(j - 1, -1, -1):
+            gates.append(Gate("CPHASE", (k, j), math.pi / float(1 << (j - k))))
+    for j in range(n // 2):
+        gates.append(Gate("SWAP", (j, n - 1 - j)))
+    return gates
+
+
+def qaoa_angles(levels: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+    """(gammas, betas) of ``qaoa_full``, each ~ U[0, pi)."""
+    rng = np.random.default_rng(seed)
+    gammas = rng.uniform(0.0, math.pi, size=levels)
+    betas = rng.uniform(0.0, math.pi, size=levels)
+    return gammas, betas
+
+
+def qaoa_full(n: int, levels: int = 5, seed: int = 9) -> List[Gate]:
+    """QAOA on the complete graph: H on every qubit, then per level RZZ(gamma)
+    on every pair and RX(beta) on every qubit; n + levels (n(n-1)/2 + n) gates."""
+    gammas, betas = qaoa_angles(levels, seed)
+    gates = [Gate("H", (q,)) for q in range(n)]
+    for lv in range(levels):
+        for i in range(n):
+            for j in range(i + 1, n):
+                gates.append(Gate("RZZ", (i, j), float(gammas[lv])))
+        for q in range(n):
+            gates.append(Gate("RX", (q,), float(betas[lv])))
+    return gates
+
+
 def layered_gate_count(n: int, layers: int) -> int:
     """Number of gates of layered(n, layers, seed)."""
     return layers * (n + n // 4 + n)
@@ -224,6 +288,15 @@ def config_circuit(name: str) -> Tuple[int, List[Gate]]:
         return 24, diag_heavy(24, 200, 2)
     if name == "layered32":        # 32 qubits, 40 layers, seed 4 -> 2880 gates
         return 32, layered(32, 40, 4)
+    if name.startswith("qaoa"):     # 5-level fully-connected QAOA, seed 9
+        n = int(name[4:])
+        return n, qaoa_full(n, 5, 9)
+    if name.startswith("qft"):      # QFT of a seeded basis state, seed 8
+        n = int(name[3:])
+        return n, qft(n, 8)
+    if name.startswith("rzz"):      # H layer + RZZ on every pair, seed 7
+        n = int(name[3:])
+        return n, rzz_full(n, 7)
     raise KeyError(name)
 
 

@@ -383,6 +383,83 @@ def test_circuit_times_inverse_28q():
     sim.close()
 
 
+@pytest.mark.parametrize("family", ["rzz", "qft", "qaoa"])
+def test_benchmark_families_full_state(oracle_mod, family):
+    """The benchmark circuits of Sec. 5 (fully-connected RZZ, QFT with its
+    closing SWAPs, 5-level fully-connected QAOA) at 14 and 15 qubits: full
+    state on the plain, staged and fully optimised paths, and in complex64."""
+    for n in (14, 15):
+        _, gates = W.config_circuit(f"{family}{n}")
+        want = oracle_mod.run(n, gates)
+        for opt in (0, qsim.OPT_STAGES | qsim.OPT_REMAP, qsim.OPT_ALL):
+            say(f"{family}{n} c128 opt={opt}")
+            got, _ = gpu_state(n, gates, opt=opt, C=12)
+            check128(got, want, f"{family}{n} opt={opt}")
+        say(f"{family}{n} c64")
+        got, _ = gpu_state(n, gates, dtype="c64", opt=qsim.OPT_ALL)
+        check64(got, want, oracle_mod, f"{family}{n} c64")
+
+
+@pytest.mark.parametrize("family", ["rzz", "qft", "qaoa"])
+def test_benchmark_families_30q_closed_form(family):
+    """The same families at 30 qubits against their closed forms (diagonal
+    phases, the Fourier kernel, QAOA weight classes) on 2^20 sampled indices."""
+    from oracle import closed_forms as CF
+    n, gates = W.config_circuit(f"{family}30")
+    idx = W.sample_indices(n, 1 << 20, 12)
+    if family == "rzz":
+        want = CF.hadamard_diagonal_amplitudes(n, gates, idx)
+    elif family == "qft":
+        want = CF.qft_amplitudes(n, CF.qft_input(n, gates), idx)
+    else:
+        want = CF.qaoa_amplitudes(n, gates, idx)
+    say(f"{family}30 c128")
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    check128(sim.amplitudes(idx), want, f"{family}30")
+    assert abs(sim.norm() - 1) < 1e-12
+    if family == "qaoa":
+        say("qaoa30 c64 vs c128")
+        b = qsim.Simulator(n, dtype="c64", opt=qsim.OPT_ALL)
+        b.load(gates)
+        b.run()
+        inf = 1 - abs(sim.inner(b)) ** 2 / (sim.norm() * b.norm())
+        say(f"qaoa30 infidelity {inf:.3e}")
+        assert inf <= 1e-6
+        b.close()
+    sim.close()
+
+
+def test_batched_small_circuits_with_swaps(oracle_mod):
+    """A solo run applies SWAPs as relabellings (the plan's layout moves); a
+    batched small-state run applies the gates as given.  Outputs of both are
+    in logical order, and so is the inner product between the two."""
+    import torch
+    cases = []
+    for n in (5, 9, 12, 13):
+        gates = W.qft(n, n) + W.random_mixed(n, 40, seed=n, max_k=3)
+        assert qsim.Plan(n, gates).layout() != list(range(n))
+        sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+        sim.load(gates)
+        cases.append((n, gates, sim, oracle_mod.run(n, gates)))
+    say("batched small circuits with SWAPs")
+    qsim.run_batch([c[2] for c in cases])
+    torch.cuda.synchronize()
+    for n, gates, sim, want in cases:
+        check128(sim.amplitudes(), want, f"batch n={n}")
+        qs = [n - 1, 0, n // 2]
+        np.testing.assert_allclose(sim.probabilities(qs), oracle_mod.marginal(want, qs), atol=1e-13)
+        solo = qsim.Simulator(n, opt=qsim.OPT_ALL)
+        solo.load(gates)
+        solo.run()
+        check128(solo.amplitudes(), want, f"solo n={n}")
+        assert abs(abs(sim.inner(solo)) - 1) < 1e-12
+        np.testing.assert_allclose(solo.probabilities(qs), oracle_mod.marginal(want, qs), atol=1e-13)
+        solo.close()
+        sim.close()
+
+
 def test_served_results_equal_solo_runs():
     """Serving loop: every request's final state equals its solo run (batched
     small circuits and overlapping large ones)."""

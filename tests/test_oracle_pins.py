@@ -10,6 +10,10 @@
   Eq. (swap gate) in Sec. 2.3.
 * Invariants: norm preservation, C * C^-1 = identity.
 * Reductions: marginals, norm and inner product against numpy.
+* Benchmark families of Sec. 5 (fully-connected RZZ, QFT, QAOA): the QFT
+  circuit against numpy's inverse FFT on random states, and the closed forms
+  used at 30 qubits against the full oracle, special cases and a second
+  derivation.
 """
 import itertools
 import math
@@ -312,6 +316,113 @@ def test_closed_forms_against_full_oracle(oracle_mod):
     np.testing.assert_allclose(CF.product_state_amplitudes(n, g, idx), oracle_mod.run(n, g), atol=1e-14)
     g2 = W.hadamard_diagonal_circuit(n, 120, seed=4)
     np.testing.assert_allclose(CF.hadamard_diagonal_amplitudes(n, g2, idx), oracle_mod.run(n, g2), atol=1e-14)
+
+
+# ---------------------------------------------------------------- benchmark families (Sec. 5)
+def _qft_only(n, seed):
+    g = W.qft(n, seed)
+    return g[sum(1 for x in g if x.kind == "X"):] if g and g[0].kind == "X" else g
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_qft_circuit_is_inverse_dft(oracle_mod, n):
+    """The QFT maps a to sqrt(2^n) * ifft(a) (numpy's convention
+    ifft(a)[y] = 2^-n sum_x a_x exp(2 pi i x y / 2^n)), on random states."""
+    gates = [g for g in _qft_only(n, 0) if g.kind != "X"]
+    assert sum(1 for g in gates if g.kind == "H") == n
+    for seed in range(3):
+        psi = random_state(n, 40 + seed)
+        got = oracle_mod.apply(n, gates, psi)
+        np.testing.assert_allclose(got, math.sqrt(1 << n) * np.fft.ifft(psi), atol=1e-13)
+
+
+def test_qft_closed_form_against_oracle(oracle_mod):
+    from oracle import closed_forms as CF
+    for n in range(1, 10):
+        for seed in range(3):
+            g = W.qft(n, seed)
+            x0 = CF.qft_input(n, g)
+            assert x0 == W.qft_input_index(n, seed)
+            want = oracle_mod.run(n, g)
+            got = CF.qft_amplitudes(n, x0, np.arange(1 << n, dtype=np.uint64))
+            assert np.max(np.abs(got - want)) < 1e-13, (n, seed)
+
+
+def test_rzz_full_against_diagonal_closed_form(oracle_mod):
+    from oracle import closed_forms as CF
+    for n in (2, 5, 9):
+        g = W.rzz_full(n, seed=n)
+        assert len(g) == n + n * (n - 1) // 2
+        idx = np.arange(1 << n, dtype=np.uint64)
+        np.testing.assert_allclose(CF.hadamard_diagonal_amplitudes(n, g, idx), oracle_mod.run(n, g), atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 10])
+def test_qaoa_symmetric_form_against_oracle(oracle_mod, n):
+    from oracle import closed_forms as CF
+    for levels, seed in ((1, 0), (3, n), (5, 9)):
+        g = W.qaoa_full(n, levels, seed)
+        want = oracle_mod.run(n, g)
+        got = CF.qaoa_amplitudes(n, g, np.arange(1 << n, dtype=np.uint64))
+        assert np.max(np.abs(got - want)) < 1e-13, (n, levels)
+
+
+def _qaoa_circuit(n, gammas, betas):
+    g = [Gate("H", (q,)) for q in range(n)]
+    for gm, bt in zip(gammas, betas):
+        g += [Gate("RZZ", (i, j), gm) for i in range(n) for j in range(i + 1, n)]
+        g += [Gate("RX", (q,), bt) for q in range(n)]
+    return g
+
+
+def test_qaoa_symmetric_form_special_cases():
+    """beta = 0 leaves H^n plus diagonals (the diagonal closed form); gamma = 0
+    leaves |+>^n, an eigenvector of every RX(b) with eigenvalue exp(-i b/2)."""
+    from oracle import closed_forms as CF
+    n = 7
+    idx = np.arange(1 << n, dtype=np.uint64)
+    g = _qaoa_circuit(n, [0.4, 1.1], [0.0, 0.0])
+    diag_only = [x for x in g if x.kind != "RX"]
+    np.testing.assert_allclose(CF.qaoa_amplitudes(n, g, idx), CF.hadamard_diagonal_amplitudes(n, diag_only, idx),
+                               atol=1e-15)
+    betas = [0.3, 2.2, 1.0]
+    g = _qaoa_circuit(n, [0.0, 0.0, 0.0], betas)
+    want = 2.0 ** (-n / 2) * np.exp(-0.5j * n * sum(betas))
+    np.testing.assert_allclose(CF.qaoa_amplitudes(n, g, idx), np.full(1 << n, want), atol=1e-15)
+
+
+def test_qaoa_30_qubits_two_derivations():
+    """The weight-class amplitudes at 30 qubits (the size they are used at)
+    against a second derivation: the RX layer as exp(-i beta J_x) with J_x the
+    collective spin operator, tridiagonal in the normalised Dicke basis
+    (<D_{w+1}| J_x |D_w> = sqrt((w + 1)(n - w)) / 2), exponentiated by eigh."""
+    from oracle import closed_forms as CF
+    n = 30
+    g = W.qaoa_full(n, 5, 9)
+    w = np.arange(n + 1)
+    binom = np.array([math.comb(n, k) for k in range(n + 1)], dtype=np.float64)
+    off = 0.5 * np.sqrt((w[:-1] + 1.0) * (n - w[:-1]))
+    ev, V = np.linalg.eigh(np.diag(off, 1) + np.diag(off, -1))
+    gammas, betas = W.qaoa_angles(5, 9)
+    d = np.full(n + 1, 2.0 ** (-n / 2.0), dtype=np.complex128) * np.sqrt(binom)
+    for gm, bt in zip(gammas, betas):
+        s = (n - 2 * w).astype(np.float64)
+        d = d * np.exp(-0.5j * gm * (s * s - n) / 2.0)
+        d = V @ (np.exp(-1j * bt * ev) * (V.T @ d))
+    c = CF.qaoa_weights(n, g)
+    assert np.max(np.abs(c - d / np.sqrt(binom))) < 1e-13
+    assert abs(np.sum(binom * np.abs(c) ** 2) - 1.0) < 1e-11
+
+
+def test_qaoa_form_rejects_other_circuits():
+    from oracle import closed_forms as CF
+    g = W.qaoa_full(5, 2, 1)
+    with pytest.raises(ValueError):
+        CF.qaoa_weights(5, g[:-1])
+    bad = list(g)
+    bad[7] = Gate("RZZ", bad[7].qubits, bad[7].theta + 0.1)
+    with pytest.raises(ValueError):
+        CF.qaoa_weights(5, bad)
 
 
 # ---------------------------------------------------------------- planted mistakes

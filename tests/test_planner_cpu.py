@@ -372,3 +372,34 @@ def test_premarshalled_circuit_plans_identically():
                 assert len(x["kernel_ops"]) == len(y["kernel_ops"])
                 for kx, ky in zip(x["kernel_ops"], y["kernel_ops"]):
                     assert np.array_equal(kx["payload"], ky["payload"])
+
+
+def test_swap_gates_become_relabellings(oracle_mod):
+    """With remapping on, a SWAP moves no data: the plan holds no op for it,
+    later gates act on the exchanged qubits and the layout records where each
+    logical qubit ended up (Sec. 2.3)."""
+    n = 11
+    gates = W.qft(n, 5) + W.random_mixed(n, 80, seed=6, max_k=3)
+    n_swaps = sum(1 for g in gates if g.kind == "SWAP")
+    assert n_swaps >= n // 2
+    want = oracle_mod.run(n, gates)
+    for opt in (qsim.OPT_ALL, qsim.OPT_REMAP | qsim.OPT_STAGES, qsim.OPT_STAGES, qsim.OPT_DIAG):
+        p = qsim.Plan(n, gates, opt=opt, C=9)
+        ops = p.ops()
+        got = run_plan(ops, n, p.layout())
+        assert np.max(np.abs(got - want)) < 1e-12, opt
+        relabel = bool(opt & qsim.OPT_REMAP)
+        assert (sorted(p.layout()) == list(range(n)))
+        assert (p.layout() != list(range(n))) == relabel
+
+
+def test_benchmark_family_plans_30q():
+    """Plan sizes of the Sec. 5 benchmark families at 30 qubits (complex128):
+    the all-pairs RZZ layer is one diagonal-only pass after the booster, the
+    QFT's closing SWAPs cost nothing, and QAOA needs about three passes a level."""
+    s = qsim.Plan(*W.config_circuit("rzz30")).stats()
+    assert s["full_passes"] == 1 and s["n_kron"] == 1
+    s = qsim.Plan(*W.config_circuit("qft30")).stats()
+    assert s["full_passes"] <= 2 and s["n_perm"] == 0
+    s = qsim.Plan(*W.config_circuit("qaoa30")).stats()
+    assert s["full_passes"] <= 16 and s["n_perm"] == 0

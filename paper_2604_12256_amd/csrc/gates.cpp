@@ -4,6 +4,7 @@
 // Sec. 4.5; CNOT and RZ in Sec. 5.1) but prints no matrices; the textbook ones
 // are used.  Matrix layout follows Sec. 2.2: bit t of the row/column index is
 // qubit q[t].
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -203,6 +204,102 @@ void apply_left(Operator &acc, const Operator &g)
             }
             for (uint64_t r = 0; r < d; ++r) acc.m[(base | off[r]) * D + col] = w[r];
         }
+}
+
+namespace {
+
+// out (a diagonal on `to`) *= d, entry by entry; d's index is the OR of a part
+// from the low `lo` bits of the entry index and a part from the high bits
+void diag_multiply_into(Operator &out, const Operator &d)
+{
+    const int K = out.k(), lo = K / 2, hi = K - lo;
+    std::vector<int> pos(d.k());
+    for (int t = 0; t < d.k(); ++t) {
+        pos[t] = -1;
+        for (int u = 0; u < K; ++u)
+            if (out.q[u] == d.q[t]) pos[t] = u;
+        if (pos[t] < 0) throw std::runtime_error("diag_product: qubit not in target list");
+    }
+    std::vector<uint32_t> tl(1u << lo), th(1u << hi);
+    for (uint32_t x = 0; x < (1u << lo); ++x) {
+        uint32_t r = 0;
+        for (int t = 0; t < d.k(); ++t)
+            if (pos[t] < lo) r |= ((x >> pos[t]) & 1u) << t;
+        tl[x] = r;
+    }
+    for (uint32_t x = 0; x < (1u << hi); ++x) {
+        uint32_t r = 0;
+        for (int t = 0; t < d.k(); ++t)
+            if (pos[t] >= lo) r |= ((x >> (pos[t] - lo)) & 1u) << t;
+        th[x] = r;
+    }
+    const cplx *dm = d.m.data();
+    for (uint32_t xh = 0; xh < (1u << hi); ++xh) {
+        const uint32_t rh = th[xh];
+        cplx *row = out.m.data() + ((uint64_t)xh << lo);
+        for (uint32_t xl = 0; xl < (1u << lo); ++xl) {
+            const cplx a = row[xl], b = dm[rh | tl[xl]];
+            row[xl] = cplx(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+        }
+    }
+}
+
+}  // namespace
+
+Operator diag_product(const std::vector<int> &to, const std::vector<const Operator *> &ds)
+{
+    const int K = (int)to.size();
+    if (K > 30) throw std::runtime_error("diag_product: too many qubits");
+    for (const Operator *d : ds)
+        if (!d->diag) throw std::runtime_error("diag_product: member not diagonal");
+    Operator out;
+    out.q = to;
+    out.diag = true;
+    out.m.assign(1ull << K, cplx(1.0, 0.0));
+    // narrow members are first multiplied into partial products on at most
+    // kP qubits (small tables), so a full-size pass is paid per partial
+    // product rather than per member
+    const int kP = 8;
+    if (K <= kP || ds.size() < 4) {
+        for (const Operator *d : ds) diag_multiply_into(out, *d);
+        return out;
+    }
+    std::vector<std::vector<int>> pq;
+    std::vector<std::vector<const Operator *>> pm;
+    for (const Operator *d : ds) {
+        if (d->k() >= kP) {
+            diag_multiply_into(out, *d);
+            continue;
+        }
+        int best = -1;
+        size_t best_size = 0;
+        for (size_t p = 0; p < pq.size(); ++p) {
+            std::vector<int> u = pq[p];
+            for (int x : d->q)
+                if (std::find(u.begin(), u.end(), x) == u.end()) u.push_back(x);
+            if ((int)u.size() <= kP && (best < 0 || u.size() < best_size)) {
+                best = (int)p;
+                best_size = u.size();
+            }
+        }
+        if (best < 0) {
+            pq.emplace_back(d->q.begin(), d->q.end());
+            pm.push_back({d});
+        } else {
+            for (int x : d->q)
+                if (std::find(pq[best].begin(), pq[best].end(), x) == pq[best].end()) pq[best].push_back(x);
+            pm[best].push_back(d);
+        }
+    }
+    for (size_t p = 0; p < pq.size(); ++p) {
+        Operator part;
+        part.q = pq[p];
+        part.diag = true;
+        part.m.assign(1ull << pq[p].size(), cplx(1.0, 0.0));
+        for (const Operator *d : pm[p]) diag_multiply_into(part, *d);
+        diag_multiply_into(out, part);
+    }
+    return out;
 }
 
 Operator compose(const Operator &a, const Operator &b)

@@ -42,6 +42,9 @@ uint64_t need_mask(const Operator &op);
 bool is_diagonal(const Operator &op);
 // The operator on the superset list `to` (every qubit of op.q must be in to).
 Operator embed(const Operator &op, const std::vector<int> &to);
+// Product of diagonal operators (every qubit of each in `to`), as a diagonal
+// on the list `to`; members multiply in list order.
+Operator diag_product(const std::vector<int> &to, const std::vector<const Operator *> &ds);
 // Returns b * a (a applied first); result on the union of their qubit lists
 // (a's qubits first, then b's new ones, in order).
 Operator compose(const Operator &a, const Operator &b);
@@ -65,6 +68,9 @@ struct KOp {
     std::vector<int> sel;             // physical qubits selecting the block (DENSE)
     std::vector<int> dq;              // DIAG: physical qubits of the table index (bit t <-> dq[t])
     std::vector<cplx> table;          // DENSE: 2^|sel| blocks of (2^k)^2; DIAG: 2^|dq| entries
+    // DIAG built from several diagonals: the members, multiplied into `table`
+    // once the plan is final (planning compares lowerings before that)
+    std::vector<Operator> members;
 };
 
 struct Phase {

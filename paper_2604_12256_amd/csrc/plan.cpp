@@ -32,18 +32,41 @@ double op_cost(bool diag, int dense_qubits, bool c64)
     return c64 ? 9510.0 : 7570.0;
 }
 
-// Device seconds of one stage-kernel operator on `amps` amplitudes.  Wide
-// diagonals (more than four qubits, from the diagonal detector) mostly have
-// selector bits on lanes, where every lane loads its own table entries:
-// about 200 microseconds more per 2^30 amplitudes (measured on the 30-qubit
-// diagonal-heavy circuit).
-double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64)
+// Diagonal table operators, by shape: table width w (qubits), k of them
+// register bits (2^k entries per thread), and whether a selector is a lane
+// bit (every lane loads its own entries) or all selectors are wave-uniform
+// (scalar loads).  Microseconds per 2^30 amplitudes, measured on MI355X as
+// the increment per operator in stages of 20 and 60 such operators.
+double diag_cost(int w, int k, bool lane, bool c64)
+{
+    static const double u128[4] = {172.0, 292.0, 354.0, 360.0}, l128[4] = {265.0, 374.0, 387.0, 444.0};
+    static const double u64[4] = {147.0, 162.0, 211.0, 226.0}, l64[4] = {155.0, 222.0, 225.0, 258.0};
+    static const double r128[6] = {0.0, 25.0, 45.0, 220.0, 420.0, 420.0}, r64[6] = {0.0, 5.0, 10.0, 15.0, 20.0, 25.0};
+    const int sel = w - k;
+    const int b = sel <= 2 ? 0 : sel <= 6 ? 1 : sel <= 10 ? 2 : 3;
+    const double base = c64 ? (lane ? l64[b] : u64[b]) : (lane ? l128[b] : u128[b]);
+    return base + (c64 ? r64[std::min(k, 5)] : r128[std::min(k, 5)]);
+}
+
+// Device seconds of one stage-kernel operator on `amps` amplitudes, in a
+// phase whose register bits sit at the physical qubits `reg` and whose lane
+// bits at `lane` (bit masks).
+double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64, uint64_t reg, uint64_t lane)
 {
     const double scale = amps / 1073741824.0 * 1e-6;
-    if (k.type == KOp::DIAG) return scale * (op_cost(true, 0, c64) + (k.dq.size() > 4 ? (c64 ? 110.0 : 200.0) : 0.0));
+    if (k.type == KOp::DIAG) {
+        int kr = 0;
+        bool ln = false;
+        for (int q : k.dq) {
+            kr += (int)((reg >> q) & 1);
+            ln |= ((lane >> q) & 1) != 0;
+        }
+        return scale * diag_cost((int)k.dq.size(), kr, ln, c64);
+    }
     const int kr = __builtin_popcount(k.reg_mask);
     return scale * op_cost(false, kr >= 3 ? reg_bits : kr, c64);
 }
+
 // Floating-point operations per amplitude: a dense k-qubit operator does 2^k
 // complex multiply-adds (8 flops each), a diagonal one complex multiply (6).
 double op_flops(bool diag, int dense_qubits) { return diag ? 6.0 : 8.0 * double(1 << dense_qubits); }
@@ -144,12 +167,9 @@ std::vector<Operator> diagonal_detector(int n, int D, const std::vector<Operator
             std::vector<int> qs;
             for (int q = 0; q < 64; ++q)
                 if ((uni >> q) & 1) qs.push_back(q);
-            Operator acc;
-            acc.q = qs;
-            acc.diag = true;
-            acc.m.assign(1ull << qs.size(), cplx(1.0, 0.0));
-            for (size_t idx : diag_list) apply_left(acc, in[idx]);
-            res.push_back(std::move(acc));
+            std::vector<const Operator *> members;
+            for (size_t idx : diag_list) members.push_back(&in[idx]);
+            res.push_back(diag_product(qs, members));
         }
         placed += diag_list.size();
         for (size_t idx : u_list) res.push_back(in[idx]);
@@ -204,7 +224,7 @@ struct Builder {
     // most two non-register qubits; selection by a lane bit is only allowed
     // for 1- and 2-bit operators (their matrices are then loaded per lane).
     void fuse_phase(Phase &ph, const std::vector<const Operator *> &gates, const std::vector<int> &reg_phys,
-                    uint64_t lane_phys, double *flops_per_amp)
+                    uint64_t lane_phys, uint64_t local_phys, double *flops_per_amp, bool reg_diags_to_z)
     {
         const int r = (int)reg_phys.size();
         auto regbit = [&](int phys) {
@@ -274,31 +294,82 @@ struct Builder {
         // when other blocks were opened after it.  A gate bridging two blocks
         // closes them.
         std::vector<Block> open;
-        // Diagonal gates on non-register qubits only commute with every open
-        // block (blocks are diagonal in their selector qubits): they are
-        // collected into one diagonal per phase, emitted when it grows too
-        // wide or at the end of the phase.
+        // Diagonal gates commute with each other, and with every open block
+        // whose content is diagonal on their qubits.  With fusion on, they are
+        // collected into one diagonal Z per phase (register qubits S, selector
+        // qubits T), which keeps that property for every open block: a gate
+        // joining Z first closes the blocks owning its register qubits, and a
+        // dense gate on a register qubit of Z emits Z first.  Z is emitted when
+        // its selectors would exceed kZsel (the kernel keeps up to 12 selector
+        // sources in registers) or its table 2^kZmax entries, and at the end of
+        // the phase.  One table lookup and one complex multiply per amplitude
+        // then serve every diagonal of the phase.
         Block Z;
-        const int kZmax = 10;
-        auto z_add = [&](const Operator &g) {
-            std::vector<int> T2 = Z.open ? Z.T : std::vector<int>();
-            for (int x : g.q)
+        struct ZMember {
+            const Operator *g;
+            uint32_t S;
+            std::vector<int> T;
+        };
+        std::vector<ZMember> zmem;
+        // a chunk reads the slice of a table its chunk bits select: at most
+        // kZloc chunk-local table qubits keep that slice (16 KiB) in L1
+        const int kZsel = 12, kZmax = 14, kZloc = c64 ? 11 : 10;
+        auto local_count = [&](uint32_t S, const std::vector<int> &T) {
+            int c = popc(S);
+            for (int x : T) c += (int)((local_phys >> x) & 1);
+            return c;
+        };
+        auto member_sets = [&](const std::vector<ZMember> &ms, uint32_t *S, std::vector<int> *T) {
+            *S = 0;
+            T->clear();
+            for (const ZMember &m : ms) {
+                *S |= m.S;
+                for (int x : m.T)
+                    if (std::find(T->begin(), T->end(), x) == T->end()) T->push_back(x);
+            }
+        };
+        auto emit_members = [&](std::vector<ZMember> &ms) {
+            if (ms.empty()) return;
+            uint32_t S;
+            std::vector<int> T;
+            member_sets(ms, &S, &T);
+            KOp k;
+            k.type = KOp::DIAG;
+            k.dq = qlist(S, T);
+            for (const ZMember &m : ms) k.members.push_back(*m.g);
+            *flops_per_amp += op_flops(true, 0);
+            ph.ops.push_back(std::move(k));
+            ms.clear();
+        };
+        auto emit_z = [&]() {
+            emit_members(zmem);
+            Z = Block();
+        };
+        auto z_add = [&](const Operator &g, uint32_t gS, const std::vector<int> &gT) {
+            std::vector<int> T2 = Z.T;
+            for (int x : gT)
                 if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
-            if (Z.open && (int)T2.size() > kZmax) {
-                emit(Z);
-                T2.assign(g.q.begin(), g.q.end());
+            uint32_t S2 = Z.S | gS;
+            if (Z.open && ((int)T2.size() > kZsel || popc(S2) + (int)T2.size() > kZmax ||
+                           local_count(S2, T2) > kZloc)) {
+                emit_z();
+                T2 = gT;
+                S2 = gS;
             }
-            if (!Z.open) {
-                Z.open = true;
-                Z.S = 0;
-                Z.T = T2;
-                Z.acc = embed(g, T2);
-                Z.indiv = op_cost(true, 0, c64);
-                return;
-            }
-            if (T2 != Z.acc.q) Z.acc = embed(Z.acc, T2);
-            apply_left(Z.acc, g);
+            Z.open = true;
+            Z.S = S2;
             Z.T = T2;
+            zmem.push_back({&g, gS, gT});
+        };
+        // the members of Z on any of the register bits `bits` leave Z (a dense
+        // gate on those bits follows them; the rest of Z commutes with it)
+        auto z_take = [&](uint32_t bits) {
+            std::vector<ZMember> taken, kept;
+            for (ZMember &m : zmem) (m.S & bits ? taken : kept).push_back(std::move(m));
+            zmem.swap(kept);
+            member_sets(zmem, &Z.S, &Z.T);
+            Z.open = !zmem.empty();
+            return taken;
         };
         auto close_all_owning = [&](uint32_t S, const std::vector<int> &T) {
             for (size_t i = 0; i < open.size();) {
@@ -328,11 +399,15 @@ struct Builder {
                 if (b >= 0) gS |= 1u << b;
                 else gT.push_back(x);
             }
-            if (g.diag && g.k() > 3) {  // a wide diagonal (diagonal detector output): its own table
+            if (g.diag && g.k() > 3) {  // a wide diagonal (diagonal detector output)
                 close_all_owning(gS, gT);
-                push_diag(g.q, g.m);
+                if (fuse) z_add(g, gS, gT);
+                else push_diag(g.q, g.m);  // its own table
                 continue;
             }
+            // diagonals of Z on g's register bits precede g
+            std::vector<ZMember> P;
+            if (fuse && !g.diag && (gS & Z.S)) P = z_take(gS);
             const double gcost = g.diag ? op_cost(true, 0, c64) : dense_cost(gS);
             // blocks owning a register qubit of g
             std::vector<size_t> own;
@@ -358,6 +433,7 @@ struct Builder {
                             if (((gS >> b) & 1) && reg_phys[b] == t) clash = true;
                 }
                 if (!clash && sel_ok && fused <= B.indiv + gcost + 1e-9) {
+                    emit_members(P);  // they commute with B's earlier gates
                     std::vector<int> l2 = qlist(S2, T2);
                     if (l2 != B.acc.q) B.acc = embed(B.acc, l2);
                     apply_left(B.acc, g);
@@ -369,6 +445,10 @@ struct Builder {
             }
             // g starts a block of its own: close every block it does not commute with
             close_all_owning(gS, gT);
+            if (fuse && g.diag && (gS == 0 || reg_diags_to_z)) {
+                z_add(g, gS, gT);
+                continue;
+            }
             const bool alone_ok = g.diag ? (int)gT.size() <= kTmaxUniform
                                          : (lane_sel(gT) ? ((int)gT.size() <= kTmaxLane && popc(kernel_mask(gS)) <= 2)
                                                          : (int)gT.size() <= kTmaxUniform);
@@ -379,16 +459,40 @@ struct Builder {
                 }
                 throw std::runtime_error("fuse_phase: dense gate needs more register bits");
             }
-            if (fuse && gS == 0 && g.diag && g.k() <= kZmax) {
-                z_add(g);
-                continue;
-            }
             Block nb;
             nb.open = true;
             nb.S = gS;
             nb.T = gT;
-            nb.acc = embed(g, qlist(gS, gT));
             nb.indiv = gcost;
+            if (!P.empty()) {
+                // fold the diagonals g follows into g's block when that costs no
+                // more than a table op of their own
+                uint32_t pS;
+                std::vector<int> pT;
+                member_sets(P, &pS, &pT);
+                const uint32_t S2 = gS | pS;
+                std::vector<int> T2 = gT;
+                for (int x : pT)
+                    if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
+                const bool ok = (lane_sel(T2) ? ((int)T2.size() <= kTmaxLane && popc(kernel_mask(S2)) <= 2)
+                                              : (int)T2.size() <= kTmaxUniform) &&
+                                dense_cost(S2) <= gcost + op_cost(true, 0, c64) + 1e-9;
+                if (ok) {
+                    std::vector<const Operator *> pm;
+                    for (const ZMember &m : P) pm.push_back(m.g);
+                    const std::vector<int> l2 = qlist(S2, T2);
+                    nb.acc = embed(diag_product(l2, pm), l2);
+                    apply_left(nb.acc, g);
+                    nb.S = S2;
+                    nb.T = T2;
+                    P.clear();
+                } else {
+                    emit_members(P);
+                    nb.acc = embed(g, qlist(gS, gT));
+                }
+            } else {
+                nb.acc = embed(g, qlist(gS, gT));
+            }
             if (!fuse || gS == 0) {  // no fusion, or a phase on non-register bits only: emit now
                 emit(nb);
                 continue;
@@ -396,7 +500,7 @@ struct Builder {
             open.push_back(std::move(nb));
         }
         for (Block &B : open) emit(B);
-        emit(Z);
+        emit_z();
     }
 
     // LDS bank order of a phase's lane bits.  The stage kernel's transposes
@@ -525,9 +629,34 @@ struct Builder {
                 tg.push_back(&all[gi]);
                 st.gates.push_back(all[gi]);
             }
-            fuse_phase(ph, tg, reg_phys, lane_phys, &fpa);
-            for (const KOp &k : ph.ops) st.est_s += kop_seconds(k, r, std::ldexp(1.0, st.buffer_qubits),
-                                                                plan.dtype == SIM_C64);
+            // narrow diagonals on register qubits either open blocks that a
+            // later dense gate can absorb, or join the phase's diagonal table
+            // (better when many share a register qubit): both are built, and
+            // the table form is kept when it is cheaper by the cost model
+            // without adding operators (per-operator overheads the marginal
+            // costs miss made more, lighter operators slower on the
+            // 30-qubit layered circuit)
+            const double amps = std::ldexp(1.0, st.buffer_qubits);
+            const bool c64 = plan.dtype == SIM_C64;
+            Phase alt = ph;
+            double f0 = 0, f1 = 0, t0 = 0, t1 = 0;
+            uint64_t local_m = 0;
+            for (int q : st.local) local_m |= 1ull << q;
+            fuse_phase(ph, tg, reg_phys, lane_phys, local_m, &f0, false);
+            uint64_t reg_m = 0;
+            for (int q : reg_phys) reg_m |= 1ull << q;
+            for (const KOp &k : ph.ops) t0 += kop_seconds(k, r, amps, c64, reg_m, lane_phys);
+            if (o.opt & SIM_OPT_FUSE) {
+                fuse_phase(alt, tg, reg_phys, lane_phys, local_m, &f1, true);
+                for (const KOp &k : alt.ops) t1 += kop_seconds(k, r, amps, c64, reg_m, lane_phys);
+                if (t1 < t0 && alt.ops.size() <= ph.ops.size()) {
+                    ph = std::move(alt);
+                    t0 = t1;
+                    f0 = f1;
+                }
+            }
+            fpa += f0;
+            st.est_s += t0;
             st.phases.push_back(std::move(ph));
             prev = st.phases.back().reg;
             rem.swap(left);
@@ -941,7 +1070,7 @@ struct Builder {
             lower_gates(buffer, nb, gates);
             double t_plain = 0;
             for (size_t i = mark; i < plan.ops.size(); ++i) t_plain += est_seconds(plan.ops[i]);
-            if (t_dd < t_plain) {
+            if (t_dd <= t_plain) {  // a tie keeps the detector: fewer, wider table members
                 plan.ops.resize(mark);
                 for (PlanOp &op : with_dd) plan.ops.push_back(std::move(op));
                 plan.stats = stats_dd;
@@ -1151,6 +1280,15 @@ void build_plan(Plan &plan, const std::vector<Operator> &gates)
         rest = in;
     }
     b.lower(0, plan.n, std::move(rest));
+    for (PlanOp &op : plan.ops)  // tables of the accumulated diagonals of the kept lowering
+        for (Phase &ph : op.phases)
+            for (KOp &k : ph.ops)
+                if (!k.members.empty()) {
+                    std::vector<const Operator *> ms;
+                    for (const Operator &g : k.members) ms.push_back(&g);
+                    k.table = diag_product(k.dq, ms).m;
+                    k.members.clear();
+                }
     if (relabel) {  // logical q carries label pi[q], which sits at bit layout[pi[q]]
         std::vector<int> lay(plan.n);
         for (int q = 0; q < plan.n; ++q) lay[q] = plan.layout[pi[q]];

@@ -403,3 +403,21 @@ def test_benchmark_family_plans_30q():
     assert s["full_passes"] <= 2 and s["n_perm"] == 0
     s = qsim.Plan(*W.config_circuit("qaoa30")).stats()
     assert s["full_passes"] <= 16 and s["n_perm"] == 0
+
+
+def test_phase_diagonals_merge_into_wide_tables(oracle_mod):
+    """Every diagonal of a register phase (narrow gates and detector outputs,
+    on register, lane, wave or chunk qubits) folds into one table of up to 12
+    selector qubits; the interpreted plan must still reproduce the oracle."""
+    n = 16
+    for gates in (W.qaoa_full(n, 2, 3), W.rzz_full(n, 4) + W.layered(n, 2, 5), W.qft(n, 6)):
+        want = oracle_mod.run(n, gates)
+        for dtype, C in (("c128", 10), ("c64", 11), ("c128", 12)):
+            p = qsim.Plan(n, gates, dtype=dtype, C=C)
+            ops = p.ops()
+            widths = [len(k["qubits"]) for o in ops if o["kind"] == "STAGE"
+                      for k in o["kernel_ops"] if k["diagonal"]]
+            assert max(widths) >= 11
+            for use_k in (True, False):
+                got = run_plan(ops, n, p.layout(), use_kernel_ops=use_k)
+                assert np.max(np.abs(got - want)) < 1e-12, (dtype, C, use_k)

@@ -153,6 +153,43 @@ sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out);
 
 sim_status sim_stats(const sim_ctx *ctx, sim_run_stats *out);
 
+/* ---- measurement (the projective model of the paper's measurement
+ * background, Sec. 2: M_i^j keeps the amplitudes whose qubit j is i, and
+ * <psi|M_i^j|psi> is the probability of outcome i) ----------------------------
+ * All require a completed run, act on the state the last run produced, take
+ * qubits and indices in logical order, and synchronise the stream.  Random
+ * numbers are inputs: u values are uniforms in [0, 1) the caller draws
+ * (SIM_E_INVAL for any other value). */
+
+/* Measure qubit `qubit`: with p0 = sum over i with bit qubit = 0 of |a_i|^2
+ * and p1 likewise (FP64, fixed order), the outcome is 0 if u < p0 / (p0 + p1)
+ * and 1 otherwise.  The state collapses in place: amplitudes of the other
+ * outcome become 0 and the kept ones are divided by sqrt(p_outcome), one
+ * pass.  *outcome (may be NULL) receives the outcome, *prob (may be NULL)
+ * its probability p_outcome / (p0 + p1). */
+sim_status sim_measure(sim_ctx *ctx, uint32_t qubit, double u, uint32_t *outcome, double *prob);
+
+/* Draw n_shots basis states by inverting the cumulative distribution in
+ * logical index order: out[s] = the smallest x whose cumulative mass
+ * sum_{y <= x} |a_y|^2 exceeds u[s] * T, T the total mass.  The result
+ * always has nonzero probability.  Cumulative sums are FP64 in a fixed order
+ * (a marginal over the top logical qubits, then in-block prefix sums), so
+ * for a u within rounding of a boundary the index next to it may come out.
+ * The state is not changed.  n_shots <= 2^31; u and out are host arrays of
+ * n_shots entries. */
+sim_status sim_sample(sim_ctx *ctx, const double *u, uint64_t n_shots, uint64_t *out);
+
+/* Expectation values of Z strings: out[k] = <psi| Z_S |psi> =
+ * sum_x |a_x|^2 (-1)^popcount(x & masks[k]), masks[k] a bit mask of logical
+ * qubits (mask 0 gives the squared norm).  One FP64 pass over the state per
+ * 16 masks; deterministic. */
+sim_status sim_expect_z(sim_ctx *ctx, const uint64_t *masks, uint32_t n_masks, double *out);
+
+/* Expectation value of a real diagonal observable on nq <= 16 qubits:
+ * *out = sum_y P(y) f[y], P the marginal of sim_probabilities over `qubits`
+ * (bit t of y <-> qubits[t]); f holds 2^nq doubles. */
+sim_status sim_expect_diagonal(sim_ctx *ctx, const uint32_t *qubits, uint32_t nq, const double *f, double *out);
+
 /* Per-op device timing: when enabled, sim_run records a pair of HIP events on
  * the context's stream around every kernel launch of the plan. */
 sim_status sim_set_profiling(sim_ctx *ctx, uint32_t enable);

@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libqsim355.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "gates.cpp", "plan.cpp", "kernels_basic.hip", "kernel_small.hip", "kernel_stage.hip",
-           "kernel_mfma.hip"]
+           "kernel_mfma.hip", "kernels_measure.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
           "-I", CSRC]

@@ -757,6 +757,175 @@ sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, do
     return SIM_OK;
 }
 
+// ---- measurement ----------------------------------------------------------
+
+sim_status sim_measure(sim_ctx *c, uint32_t qubit, double u, uint32_t *outcome, double *prob)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
+    if ((int)qubit >= c->n) return fail(c, SIM_E_INVAL, "qubit out of range");
+    if (!(u >= 0.0 && u < 1.0)) return fail(c, SIM_E_INVAL, "u must lie in [0, 1)");
+    double bins[2];
+    sim_status st = sim_probabilities(c, &qubit, 1, bins);
+    if (st != SIM_OK) return st;
+    const double total = bins[0] + bins[1];
+    if (!(total > 0.0)) return fail(c, SIM_E_STATE, "state has zero norm");
+    const int m = u < bins[0] / total ? 0 : 1;
+    const double pm = bins[m];
+    const double scale = 1.0 / std::sqrt(pm);
+    hipError_t e = c->dtype == SIM_C128 ? qs::launch_collapse<double>(c->state, c->n, c->layout[qubit], m, scale,
+                                                                      c->stream)
+                                        : qs::launch_collapse<float>(c->state, c->n, c->layout[qubit], m, scale,
+                                                                     c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "collapse");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    if (outcome) *outcome = (uint32_t)m;
+    if (prob) *prob = pm / total;
+    return SIM_OK;
+}
+
+sim_status sim_sample(sim_ctx *c, const double *u, uint64_t n_shots, uint64_t *out)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
+    if (n_shots == 0) return SIM_OK;
+    if (!u || !out) return fail(c, SIM_E_INVAL, "u or out is NULL");
+    if (n_shots > (1ull << 31)) return fail(c, SIM_E_INVAL, "at most 2^31 shots per call");
+    for (uint64_t i = 0; i < n_shots; ++i)
+        if (!(u[i] >= 0.0 && u[i] < 1.0)) return fail(c, SIM_E_INVAL, "every u must lie in [0, 1)");
+    const int n = c->n;
+    const int K = n >= 9 ? std::min(16, n - 8) : 0;  // top logical qubits resolved by a marginal
+    const int nlow = n - K;
+    std::vector<uint32_t> top(K);
+    for (int t = 0; t < K; ++t) top[t] = (uint32_t)(nlow + t);
+    std::vector<double> bins((size_t)1 << K);
+    sim_status st = sim_probabilities(c, top.data(), (uint32_t)K, bins.data());
+    if (st != SIM_OK) return st;
+    std::vector<double> C(bins.size());
+    double acc = 0.0;
+    for (size_t b = 0; b < bins.size(); ++b) C[b] = (acc += bins[b]);
+    const double T = acc;
+    if (!(T > 0.0)) return fail(c, SIM_E_STATE, "state has zero norm");
+    size_t last_pos = 0;
+    for (size_t b = 0; b < bins.size(); ++b)
+        if (bins[b] > 0.0) last_pos = b;
+    // block and residual per shot; the block is the first whose cumulative
+    // mass exceeds u T
+    std::vector<uint64_t> blk(n_shots);
+    std::vector<double> res(n_shots);
+    for (uint64_t i = 0; i < n_shots; ++i) {
+        const double t = u[i] * T;
+        size_t b = (size_t)(std::upper_bound(C.begin(), C.end(), t) - C.begin());
+        if (b >= C.size()) {
+            b = last_pos;
+            res[i] = bins[b];  // past every block: the block's last amplitude with mass
+        } else {
+            res[i] = t - (b ? C[b - 1] : 0.0);
+        }
+        blk[i] = b;
+    }
+    std::vector<uint32_t> order(n_shots);
+    for (uint64_t i = 0; i < n_shots; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return blk[a] < blk[b]; });
+    std::vector<uint64_t> ids, bases;
+    std::vector<uint32_t> start;
+    std::vector<double> rs(n_shots);
+    for (uint64_t j = 0; j < n_shots; ++j) {
+        const uint64_t b = blk[order[j]];
+        if (ids.empty() || ids.back() != b) {
+            ids.push_back(b);
+            start.push_back((uint32_t)j);
+            uint64_t base = 0;
+            for (int t = 0; t < K; ++t) base |= ((b >> t) & 1ull) << c->layout[nlow + t];
+            bases.push_back(base);
+        }
+        rs[j] = res[order[j]];
+    }
+    start.push_back((uint32_t)n_shots);
+    std::vector<uint64_t> tabs(1024, 0);
+    for (uint32_t w = 0; w < 512; ++w)
+        for (int q = 0; q < 9; ++q) {
+            if (q < nlow && ((w >> q) & 1)) tabs[w] |= 1ull << c->layout[q];
+            if (9 + q < nlow && ((w >> q) & 1)) tabs[512 + w] |= 1ull << c->layout[9 + q];
+        }
+    qs::SampleArgs S{};
+    S.nlow = nlow;
+    S.nthr = nlow >= 8 ? 256 : (1 << nlow);
+    S.seg_log2 = nlow >= 8 ? nlow - 8 : 0;
+    const size_t nb = ids.size();
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_tabs = 0, o_bases = o_tabs + al(1024 * 8), o_ids = o_bases + al(nb * 8),
+                 o_start = o_ids + al(nb * 8), o_res = o_start + al((nb + 1) * 4), o_out = o_res + al(n_shots * 8),
+                 total = o_out + al(n_shots * 8);
+    HIPCHK(c, grow(c->io, total), "sample buffers");
+    char *d = (char *)c->io.p;
+    HIPCHK(c, hipMemcpyAsync(d + o_tabs, tabs.data(), 1024 * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    HIPCHK(c, hipMemcpyAsync(d + o_bases, bases.data(), nb * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    HIPCHK(c, hipMemcpyAsync(d + o_ids, ids.data(), nb * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    HIPCHK(c, hipMemcpyAsync(d + o_start, start.data(), (nb + 1) * 4, hipMemcpyHostToDevice, c->stream), "upload");
+    HIPCHK(c, hipMemcpyAsync(d + o_res, rs.data(), n_shots * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    hipError_t e = c->dtype == SIM_C128
+                       ? qs::launch_sample<double>(c->state, S, (uint32_t)nb, (const uint64_t *)(d + o_tabs),
+                                                   (const uint64_t *)(d + o_bases), (const uint64_t *)(d + o_ids),
+                                                   (const uint32_t *)(d + o_start), (const double *)(d + o_res),
+                                                   (uint64_t *)(d + o_out), c->stream)
+                       : qs::launch_sample<float>(c->state, S, (uint32_t)nb, (const uint64_t *)(d + o_tabs),
+                                                  (const uint64_t *)(d + o_bases), (const uint64_t *)(d + o_ids),
+                                                  (const uint32_t *)(d + o_start), (const double *)(d + o_res),
+                                                  (uint64_t *)(d + o_out), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sample");
+    std::vector<uint64_t> sorted_out(n_shots);
+    HIPCHK(c, hipMemcpyAsync(sorted_out.data(), d + o_out, n_shots * 8, hipMemcpyDeviceToHost, c->stream),
+           "copy out");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    for (uint64_t j = 0; j < n_shots; ++j) out[order[j]] = sorted_out[j];
+    return SIM_OK;
+}
+
+sim_status sim_expect_z(sim_ctx *c, const uint64_t *masks, uint32_t n_masks, double *out)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
+    if (n_masks == 0) return SIM_OK;
+    if (!masks || !out) return fail(c, SIM_E_INVAL, "masks or out is NULL");
+    const uint64_t all = c->n >= 64 ? ~0ull : ((1ull << c->n) - 1);
+    for (uint32_t i = 0; i < n_masks; ++i)
+        if (masks[i] & ~all) return fail(c, SIM_E_INVAL, "mask names a qubit out of range");
+    const size_t scr = qs::expect_z_scratch_bytes();
+    HIPCHK(c, grow(c->scratch, scr + 64 * 8 + 256), "scratch allocation");
+    double *dout = (double *)((char *)c->scratch.p + ((scr + 255) / 256) * 256);
+    for (uint32_t i0 = 0; i0 < n_masks; i0 += qs::kZMasksPerLaunch) {
+        qs::ZArgs Z{};
+        Z.nm = (int32_t)std::min<uint32_t>(qs::kZMasksPerLaunch, n_masks - i0);
+        for (int k = 0; k < Z.nm; ++k) {
+            uint64_t pm = 0;
+            for (int q = 0; q < c->n; ++q)
+                if ((masks[i0 + k] >> q) & 1) pm |= 1ull << c->layout[q];
+            Z.m[k] = pm;
+        }
+        hipError_t e = c->dtype == SIM_C128
+                           ? qs::launch_expect_z<double>(c->state, c->n, Z, dout, (double *)c->scratch.p, c->stream)
+                           : qs::launch_expect_z<float>(c->state, c->n, Z, dout, (double *)c->scratch.p, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "expectation");
+        HIPCHK(c, hipMemcpyAsync(out + i0, dout, Z.nm * 8, hipMemcpyDeviceToHost, c->stream), "copy out");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    }
+    return SIM_OK;
+}
+
+sim_status sim_expect_diagonal(sim_ctx *c, const uint32_t *qubits, uint32_t nq, const double *f, double *out)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!f || !out) return fail(c, SIM_E_INVAL, "f or out is NULL");
+    std::vector<double> bins((size_t)1 << std::min<uint32_t>(nq, 16));
+    sim_status st = sim_probabilities(c, qubits, nq, bins.data());
+    if (st != SIM_OK) return st;
+    double acc = 0.0;
+    for (size_t y = 0; y < bins.size(); ++y) acc += bins[y] * f[y];
+    *out = acc;
+    return SIM_OK;
+}
+
 sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out)
 {
     if (!a || !b) return SIM_E_INVAL;

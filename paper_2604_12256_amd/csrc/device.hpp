@@ -149,4 +149,27 @@ template <typename R> hipError_t launch_stage(const StageLaunch &L, hipStream_t 
 
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
 
+// ---- measurement (kernels_measure.hip) ----
+// Inverse-CDF sampling inside blocks of 2^nlow consecutive logical indices:
+// nthr threads each own 2^seg_log2 of them (nthr << seg_log2 == 2^nlow).
+// The physical address of within-block offset w is
+// base | tabs[w & 511] | tabs[512 + (w >> 9)] (nlow <= 18).
+struct SampleArgs {
+    int32_t nlow, seg_log2, nthr, pad;
+};
+constexpr int kZMasksPerLaunch = 16;
+struct ZArgs {
+    uint64_t m[kZMasksPerLaunch];   // physical qubit masks of the Z strings
+    int32_t nm, pad;
+};
+template <typename R> hipError_t launch_collapse(void *state, int n, int phys_qubit, int outcome, double scale,
+                                                 hipStream_t s);
+template <typename R> hipError_t launch_sample(const void *state, const SampleArgs &S, uint32_t nblocks,
+                                               const uint64_t *tabs, const uint64_t *bases, const uint64_t *ids,
+                                               const uint32_t *start, const double *resid, uint64_t *out,
+                                               hipStream_t s);
+size_t expect_z_scratch_bytes();
+template <typename R> hipError_t launch_expect_z(const void *state, int n, const ZArgs &Z, double *out,
+                                                 double *scratch, hipStream_t s);
+
 }  // namespace qs

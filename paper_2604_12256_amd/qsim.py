@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Iterable, List, Optional, Sequence
+from typing import Iterable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -115,6 +115,10 @@ def load_library() -> ctypes.CDLL:
         "sim_plan_destroy": (I, [P]),
         "sim_version": (ctypes.c_char_p, []),
         "sim_device_copy": (I, [P, P, U64, P]),
+        "sim_measure": (I, [P, U32, ctypes.c_double, P, P]),
+        "sim_sample": (I, [P, P, U64, P]),
+        "sim_expect_z": (I, [P, P, U32, P]),
+        "sim_expect_diagonal": (I, [P, P, U32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -234,6 +238,42 @@ class Simulator:
         out = np.empty(2, dtype=np.float64)
         self._check(self._lib.sim_inner(self._ctx, other._ctx, out.ctypes.data))
         return complex(out[0], out[1])
+
+    def measure(self, qubit: int, u: float) -> Tuple[int, float]:
+        """Projective measurement of one qubit with the caller's uniform u in
+        [0, 1); the state collapses in place.  Returns (outcome, probability)."""
+        m = ctypes.c_uint32()
+        p = ctypes.c_double()
+        self._check(self._lib.sim_measure(self._ctx, int(qubit), float(u), ctypes.byref(m), ctypes.byref(p)))
+        return int(m.value), float(p.value)
+
+    def sample(self, u: np.ndarray) -> np.ndarray:
+        """Basis states for the uniforms u (inverse cumulative distribution in
+        logical index order)."""
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        out = np.empty(u.size, dtype=np.uint64)
+        if u.size:
+            self._check(self._lib.sim_sample(self._ctx, u.ctypes.data, u.size, out.ctypes.data))
+        return out
+
+    def expect_z(self, masks: Sequence[int]) -> np.ndarray:
+        """<psi| Z_S |psi> for every logical qubit mask S."""
+        m = np.ascontiguousarray(np.asarray(list(masks), dtype=np.uint64))
+        out = np.empty(m.size, dtype=np.float64)
+        if m.size:
+            self._check(self._lib.sim_expect_z(self._ctx, m.ctypes.data, m.size, out.ctypes.data))
+        return out
+
+    def expect_diagonal(self, qubits: Sequence[int], f: np.ndarray) -> float:
+        """sum_y P(y) f[y] over the marginal of `qubits`."""
+        q = np.ascontiguousarray(np.asarray(list(qubits), dtype=np.uint32))
+        f = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        if f.size != (1 << len(q)):
+            raise ValueError("f must hold 2^len(qubits) values")
+        out = ctypes.c_double()
+        self._check(self._lib.sim_expect_diagonal(self._ctx, q.ctypes.data if len(q) else None, len(q),
+                                                  f.ctypes.data, ctypes.byref(out)))
+        return float(out.value)
 
     def stats(self) -> dict:
         s = SimRunStats()

@@ -1,0 +1,163 @@
+"""GPU parity of the measurement calls (collapse, shot sampling, Z-string and
+diagonal expectations) against oracle/measure.py, through the C ABI.
+
+Tolerances: probabilities and expectations 1e-12 (FP64 sums of the same
+|a|^2 in another order); collapsed complex128 states 1e-12.  A sampled index
+must equal the oracle's unless u T lies within 1e-12 of a cumulative
+boundary, and must then still be valid: nonzero probability, and u T inside
+its cumulative interval widened by 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_12256_amd import qsim
+from paper_2604_12256_amd import workloads as W
+from paper_2604_12256_amd.workloads import Gate
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(n, gates, dtype="c128", opt=qsim.OPT_ALL):
+    sim = qsim.Simulator(n, dtype=dtype, opt=opt)
+    sim.load(gates)
+    sim.run()
+    return sim
+
+
+def check_samples(got, want, state, u, tol=1e-12):
+    from oracle import measure as M
+    c = M.cdf(state)
+    T = c[-1]
+    p = np.abs(state) ** 2
+    bad = np.nonzero(got != want)[0]
+    for i in bad:
+        x = int(got[i])
+        lo = c[x - 1] if x else 0.0
+        assert p[x] > 0 and lo - tol <= u[i] * T < c[x] + tol, (i, x, int(want[i]))
+    assert bad.size <= max(2, u.size // 1000), bad.size
+
+
+def circuits(n):
+    yield "layered", W.layered(n, 4, seed=n)
+    yield "qft+random", W.qft(n, 3) + W.random_mixed(n, 30, seed=n, max_k=3)   # moved layout
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_measure_sequence_matches_oracle(oracle_mod, dtype):
+    from oracle import measure as M
+    n = 14
+    for name, gates in circuits(n):
+        say(f"measure {name} {dtype}")
+        sim = run(n, gates, dtype)
+        ref = sim.amplitudes() if dtype == "c64" else oracle_mod.run(n, gates)
+        for q, u in ((3, 0.21), (13, 0.77), (0, 0.5), (7, 0.05)):
+            m_ref, p_ref, ref = M.measure(ref, q, u)
+            if abs(u - (p_ref if m_ref == 0 else 1 - p_ref)) < 1e-9:
+                continue
+            m, p = sim.measure(q, u)
+            assert m == m_ref and abs(p - p_ref) < (1e-12 if dtype == "c128" else 1e-6)
+            got = sim.amplitudes()
+            if dtype == "c128":
+                assert np.max(np.abs(got - ref)) < 1e-12
+            else:
+                ref = got.astype(np.complex128)  # follow the device's own single-precision state
+        assert abs(sim.norm() - 1) < (1e-12 if dtype == "c128" else 1e-6)
+        sim.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sample_matches_oracle(oracle_mod, dtype):
+    from oracle import measure as M
+    rng = np.random.default_rng(11)
+    for n in (1, 3, 7, 9, 16, 20):
+        for name, gates in circuits(n):
+            say(f"sample n={n} {name} {dtype}")
+            sim = run(n, gates, dtype)
+            state = sim.amplitudes().astype(np.complex128)
+            if dtype == "c128":
+                assert np.max(np.abs(state - oracle_mod.run(n, gates))) < 1e-12
+            u = rng.random(20000)
+            got = sim.sample(u)
+            check_samples(got, M.sample(state, u), state, u)
+            sim.close()
+
+
+def test_sample_30q_closed_forms():
+    """H on every qubit: x = floor(u 2^30) for u inside a cell; GHZ: u < 1/2
+    gives 0 and u >= 1/2 gives 2^30 - 1."""
+    n = 30
+    say("sample uniform 30q")
+    sim = run(n, [Gate("H", (q,)) for q in range(n)])
+    rng = np.random.default_rng(5)
+    k = rng.integers(0, 1 << n, size=100000, dtype=np.uint64)
+    u = (k.astype(np.float64) + 0.5) / float(1 << n)
+    np.testing.assert_array_equal(sim.sample(u), k)
+    sim.close()
+    say("sample GHZ 30q")
+    gates = [Gate("H", (0,))] + [Gate("CNOT", (q, q + 1)) for q in range(n - 1)]
+    sim = run(n, gates)
+    u = np.concatenate([rng.random(5000) * 0.4999, 0.5001 + rng.random(5000) * 0.4998])
+    got = sim.sample(u)
+    assert np.all(got[:5000] == 0) and np.all(got[5000:] == (1 << n) - 1)
+    m, p = sim.measure(17, 0.7)
+    assert m == 1 and abs(p - 0.5) < 1e-12
+    amp = sim.amplitudes(np.array([0, (1 << n) - 1], dtype=np.uint64))
+    assert abs(amp[0]) < 1e-15 and abs(abs(amp[1]) - 1) < 1e-12
+    sim.close()
+
+
+def test_expect_z_matches_oracle(oracle_mod):
+    from oracle import measure as M
+    n = 15
+    rng = np.random.default_rng(2)
+    masks = [0, 1, 1 << 14, (1 << n) - 1, 0b101010101010101] + [int(x) for x in rng.integers(0, 1 << n, 30)]
+    for name, gates in circuits(n):
+        for dtype in ("c128", "c64"):
+            say(f"expect_z {name} {dtype}")
+            sim = run(n, gates, dtype)
+            state = sim.amplitudes().astype(np.complex128)
+            np.testing.assert_allclose(sim.expect_z(masks), M.expect_z(state, masks), atol=1e-12)
+            qs, f = [14, 2, 9], rng.standard_normal(8)
+            assert abs(sim.expect_diagonal(qs, f) - M.expect_diagonal(state, qs, f)) < 1e-12
+            sim.close()
+
+
+def test_expect_z_30q_closed_forms():
+    from oracle import closed_forms as CF
+    n = 30
+    gates = W.product_circuit(n, 3, seed=21)
+    f = CF.product_state_factors(n, gates)
+    masks = [1, 1 << 29, (1 << n) - 1, 0x15555555, 0x2AAAAAAA]
+    want = [np.prod([abs(f[q][0]) ** 2 - abs(f[q][1]) ** 2 for q in range(n) if (m >> q) & 1]) for m in masks]
+    say("expect_z product 30q")
+    sim = run(n, gates)
+    np.testing.assert_allclose(sim.expect_z(masks), want, atol=1e-12)
+    sim.close()
+
+
+def test_measurement_errors():
+    n = 4
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load([Gate("H", (0,))])
+    with pytest.raises(qsim.QsimError):
+        sim.measure(0, 0.5)      # not run yet
+    sim.run()
+    for bad in (-0.1, 1.0, float("nan")):
+        with pytest.raises(qsim.QsimError):
+            sim.measure(0, bad)
+        with pytest.raises(qsim.QsimError):
+            sim.sample(np.array([0.5, bad]))
+    with pytest.raises(qsim.QsimError):
+        sim.measure(n, 0.5)
+    with pytest.raises(qsim.QsimError):
+        sim.expect_z([1 << n])
+    assert sim.sample(np.array([])).size == 0
+    sim.close()

@@ -14,6 +14,11 @@
   circuit against numpy's inverse FFT on random states, and the closed forms
   used at 30 qubits against the full oracle, special cases and a second
   derivation.
+* Measurement (Sec. 2's projective model): collapse against the literal
+  kron lift of the projector |i><i| on qubit j; sampling against closed
+  forms (uniform, GHZ, basis states) and brute-force interval counting;
+  Z-string expectations against the kron lift of Pauli Z and product-state
+  closed forms.
 """
 import itertools
 import math
@@ -423,6 +428,114 @@ def test_qaoa_form_rejects_other_circuits():
     bad[7] = Gate("RZZ", bad[7].qubits, bad[7].theta + 0.1)
     with pytest.raises(ValueError):
         CF.qaoa_weights(5, bad)
+
+
+# ---------------------------------------------------------------- measurement (Sec. 2)
+def test_collapse_matches_paper_projector(oracle_mod):
+    from oracle import measure as M
+    n = 5
+    proj = [np.array([[1, 0], [0, 0]], dtype=np.complex128), np.array([[0, 0], [0, 1]], dtype=np.complex128)]
+    for seed in range(4):
+        psi = random_state(n, 60 + seed)
+        for j in range(n):
+            for u in (0.05, 0.5, 0.95):
+                m, p, out = M.measure(psi, j, u)
+                lifted = [lift_single_paper(n, j, proj[i]) @ psi for i in (0, 1)]
+                probs = [float(np.vdot(v, v).real) for v in lifted]
+                assert m == (0 if u < probs[0] else 1)
+                assert abs(p - probs[m]) < 1e-14
+                np.testing.assert_allclose(out, lifted[m] / np.sqrt(probs[m]), atol=1e-14)
+
+
+def test_collapse_closed_forms(oracle_mod):
+    from oracle import measure as M
+    n = 6
+    ghz = np.zeros(1 << n, dtype=np.complex128)
+    ghz[0] = ghz[-1] = 1 / math.sqrt(2)
+    for q in range(n):
+        m, p, out = M.measure(ghz, q, 0.3)
+        assert (m, abs(p - 0.5) < 1e-15) == (0, True) and abs(out[0] - 1) < 1e-15
+        m, p, out = M.measure(ghz, q, 0.7)
+        assert m == 1 and abs(out[-1] - 1) < 1e-15
+    # product state: qubit q's factor becomes the basis vector of the outcome
+    from oracle import closed_forms as CF
+    g = W.product_circuit(n, 3, seed=12)
+    f = CF.product_state_factors(n, g)
+    psi = oracle_mod.run(n, g)
+    m, p, out = M.measure(psi, 2, 0.4)
+    assert abs(p - abs(f[2][m]) ** 2) < 1e-14
+    f2 = f.copy()
+    f2[2] = 0
+    f2[2][m] = f[2][m] / abs(f[2][m])
+    idx = np.arange(1 << n, dtype=np.uint64)
+    want = np.ones(1 << n, dtype=np.complex128)
+    for q in range(n):
+        want *= f2[q][((idx >> np.uint64(q)) & np.uint64(1)).astype(np.int64)]
+    np.testing.assert_allclose(out, want, atol=1e-14)
+
+
+def test_sampling_closed_forms():
+    from oracle import measure as M
+    n = 8
+    uni = np.full(1 << n, 2.0 ** (-n / 2), dtype=np.complex128)
+    k = np.arange(1 << n)
+    np.testing.assert_array_equal(M.sample(uni, (k + 0.5) / (1 << n)), k)
+    np.testing.assert_array_equal(M.sample(uni, k / (1 << n)), k)
+    ghz = np.zeros(1 << n, dtype=np.complex128)
+    ghz[0] = ghz[-1] = 1 / math.sqrt(2)
+    np.testing.assert_array_equal(M.sample(ghz, [0.0, 0.2, 0.4999, 0.5, 0.9]), [0, 0, 0, (1 << n) - 1, (1 << n) - 1])
+    basis = np.zeros(1 << n, dtype=np.complex128)
+    basis[77] = 1j
+    np.testing.assert_array_equal(M.sample(basis, np.linspace(0, 0.999, 50)), np.full(50, 77))
+
+
+def test_sampling_by_interval_counting():
+    """On a sparse random state, every u lands on the index whose cumulative
+    interval [c_{x-1}, c_x) holds u T (brute force per index), and never on a
+    zero-probability index."""
+    from oracle import measure as M
+    rng = np.random.default_rng(3)
+    n = 6
+    psi = random_state(n, 70)
+    psi[rng.random(1 << n) < 0.4] = 0
+    p = np.abs(psi) ** 2
+    u = (np.arange(4000) + 0.5) / 4000
+    got = M.sample(psi, u)
+    T = p.sum()
+    for i, x in enumerate(got):
+        lo = sum(p[:x])
+        assert p[x] > 0 and lo <= u[i] * T + 1e-15 and u[i] * T < lo + p[x] + 1e-15
+
+
+def test_expect_z_against_pauli_lift(oracle_mod):
+    from oracle import measure as M
+    n = 5
+    Zm = np.diag([1.0, -1.0])
+    for seed in range(3):
+        psi = random_state(n, 80 + seed)
+        masks = [0, 1, 0b10110, (1 << n) - 1, 0b01001]
+        for m, val in zip(masks, M.expect_z(psi, masks)):
+            op = np.eye(1)
+            for q in range(n - 1, -1, -1):  # kron order: qubit n-1 is the leftmost factor (Sec. 2.2)
+                op = np.kron(op, Zm if (m >> q) & 1 else np.eye(2))
+            assert abs(val - np.vdot(psi, op @ psi).real) < 1e-13
+    # product states: the expectation factorises
+    from oracle import closed_forms as CF
+    g = W.product_circuit(n, 3, seed=4)
+    f = CF.product_state_factors(n, g)
+    psi = oracle_mod.run(n, g)
+    for m in (0b1, 0b10101, 0b11111):
+        want = np.prod([abs(f[q][0]) ** 2 - abs(f[q][1]) ** 2 for q in range(n) if (m >> q) & 1])
+        assert abs(M.expect_z(psi, [m])[0] - want) < 1e-13
+
+
+def test_expect_diagonal_against_marginal(oracle_mod):
+    from oracle import measure as M
+    n = 7
+    psi = random_state(n, 90)
+    qs = [5, 1, 3]
+    f = np.random.default_rng(1).standard_normal(8)
+    assert abs(M.expect_diagonal(psi, qs, f) - float(np.dot(oracle_mod.marginal(psi, qs), f))) < 1e-14
 
 
 # ---------------------------------------------------------------- planted mistakes

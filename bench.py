@@ -161,7 +161,8 @@ def kernel_table(n=30):
     kernel driven through the C ABI: full-pass dense gates on the VALU
     (k = 1..3) and on MFMA (k = 4, 5), full-pass diagonals, the tensor
     product of the merge booster, |0...0>, the output reductions (marginal,
-    inner product, amplitude gather) and the batched small-state kernel.
+    inner product, amplitude gather), measurement (sampling, Z strings,
+    collapse) and the batched small-state kernel.
     Rates are algorithmic bytes (one read and one write of the state for a
     pass) over the measured time."""
     import numpy as np
@@ -231,8 +232,18 @@ def kernel_table(n=30):
         idx = np.sort(rng.choice(1 << n, 1 << 20, replace=False)).astype(np.uint64)
         add("k_gather", "2^20 sampled amplitudes incl. host index upload and copy-out",
             events(lambda: sim.amplitudes(idx)), (1 << 20) * b)
-        sim.close()
         sim2.close()
+        # measurement on the uniform state (every block of the sampler is hit)
+        sim.load([Gate("H", (q,)) for q in range(n)])
+        sim.run()
+        u = rng.random(100000)
+        add("k_marg + k_sample", "10^5 shots, uniform state, incl. host sort and copies",
+            events(lambda: sim.sample(u)), 2 * state_bytes)
+        masks = [int(x) for x in rng.integers(0, 1 << n, 16)]
+        add("k_expect_z_*", "16 Z strings, one pass", events(lambda: sim.expect_z(masks)), state_bytes)
+        add("k_marg + k_collapse", "measure one qubit (marginal, then collapse in place)",
+            events(lambda: sim.measure(5, 0.3), reps=1), 3 * state_bytes)
+        sim.close()
         del a, other
         torch.cuda.empty_cache()
         # batched small circuits: 128 circuits of 12 qubits, 20 layers each

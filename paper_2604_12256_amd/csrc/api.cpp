@@ -824,9 +824,11 @@ sim_status sim_sample(sim_ctx *c, const double *u, uint64_t n_shots, uint64_t *o
         }
         blk[i] = b;
     }
-    std::vector<uint32_t> order(n_shots);
-    for (uint64_t i = 0; i < n_shots; ++i) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return blk[a] < blk[b]; });
+    // shots grouped by block (counting sort, stable)
+    std::vector<uint32_t> count(bins.size() + 1, 0), order(n_shots);
+    for (uint64_t i = 0; i < n_shots; ++i) ++count[blk[i] + 1];
+    for (size_t b = 0; b < bins.size(); ++b) count[b + 1] += count[b];
+    for (uint64_t i = 0; i < n_shots; ++i) order[count[blk[i]]++] = (uint32_t)i;
     std::vector<uint64_t> ids, bases;
     std::vector<uint32_t> start;
     std::vector<double> rs(n_shots);

@@ -14,9 +14,16 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Grids hold at most 2^22 workgroups (2^30 work-items, inside the 32-bit
+// dispatch size); kernels loop over the rest with a grid stride, so states
+// of more than 2^32 amplitudes (33 and 34 qubits in complex128 fit in HBM)
+// run with the same kernels.  Up to 30 qubits no grid reaches the cap.
+constexpr uint64_t kMaxBlocks = 1ull << 22;
+
 uint32_t blocks_for(uint64_t work, uint64_t per_block)
 {
     uint64_t b = (work + per_block - 1) / per_block;
+    if (b > kMaxBlocks) b = kMaxBlocks;
     return (uint32_t)(b ? b : 1);
 }
 
@@ -26,15 +33,17 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_init(c2_t<R> *__restrict__ a, uint64_t len)
 {
     using V = c2_t<R>;
-    const uint64_t i0 = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * 4;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x; i0 < len; i0 += stride) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const uint64_t i = i0 + (uint64_t)u * kBlock;
-        if (i < len) {
-            V v;
-            v.x = i == 0 ? R(1) : R(0);
-            v.y = R(0);
-            a[i] = v;
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kBlock;
+            if (i < len) {
+                V v;
+                v.x = i == 0 ? R(1) : R(0);
+                v.y = R(0);
+                a[i] = v;
+            }
         }
     }
 }
@@ -49,27 +58,28 @@ __global__ __launch_bounds__(kBlock) void k_dense(c2_t<R> *__restrict__ a, const
     using V = c2_t<R>;
     const QS_CONST R *m = as_const(reinterpret_cast<const R *>(mg));
     constexpr int D = 1 << K;
-    const uint64_t grp = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (grp >= ngroups) return;
-    const uint64_t base = insert_zeros<K>(grp, g.sorted);
-    uint64_t off[D];
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t grp = (uint64_t)blockIdx.x * kBlock + threadIdx.x; grp < ngroups; grp += stride) {
+        const uint64_t base = insert_zeros<K>(grp, g.sorted);
+        uint64_t off[D];
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        uint64_t o = 0;
+        for (int r = 0; r < D; ++r) {
+            uint64_t o = 0;
 #pragma unroll
-        for (int t = 0; t < K; ++t)
-            if ((r >> t) & 1) o |= 1ull << g.q[t];
-        off[r] = base | o;
-    }
-    V v[D];
+            for (int t = 0; t < K; ++t)
+                if ((r >> t) & 1) o |= 1ull << g.q[t];
+            off[r] = base | o;
+        }
+        V v[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) v[c] = a[off[c]];
+        for (int c = 0; c < D; ++c) v[c] = a[off[c]];
 #pragma unroll
-    for (int r = 0; r < D; ++r) {
-        V acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
+        for (int r = 0; r < D; ++r) {
+            V acc = cmul(ldc<R>(m, (uint64_t)(r * D)), v[0]);
 #pragma unroll
-        for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
-        a[off[r]] = acc;
+            for (int c = 1; c < D; ++c) cmac(acc, ldc<R>(m, (uint64_t)(r * D + c)), v[c]);
+            a[off[r]] = acc;
+        }
     }
 }
 
@@ -82,24 +92,27 @@ __global__ __launch_bounds__(kBlock) void k_dense6(c2_t<R> *__restrict__ a, cons
 {
     using V = c2_t<R>;
     __shared__ V tile[kBlock];
-    const uint64_t grp = (uint64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
     const uint32_t r = threadIdx.x & 63;
-    const bool valid = grp < ngroups;
-    uint64_t base = 0, mine = 0;
-    if (valid) {
-        base = insert_zeros<6>(grp, g.sorted);
-        mine = base;
+    // the loop bound is uniform across the workgroup (barriers inside)
+    for (uint64_t g0 = (uint64_t)blockIdx.x * (kBlock / 64); g0 < ngroups; g0 += (uint64_t)gridDim.x * (kBlock / 64)) {
+        const uint64_t grp = g0 + threadIdx.x / 64;
+        const bool valid = grp < ngroups;
+        uint64_t mine = 0;
+        if (valid) {
+            mine = insert_zeros<6>(grp, g.sorted);
 #pragma unroll
-        for (int t = 0; t < 6; ++t)
-            if ((r >> t) & 1) mine |= 1ull << g.q[t];
-        tile[threadIdx.x] = a[mine];
-    }
-    __syncthreads();
-    if (valid) {
-        const V *in = tile + (threadIdx.x & ~63u);
-        V acc = cmul(ldc<R>(m, (uint64_t)r * 64), in[0]);
-        for (int c = 1; c < 64; ++c) cmac(acc, ldc<R>(m, (uint64_t)r * 64 + c), in[c]);
-        a[mine] = acc;
+            for (int t = 0; t < 6; ++t)
+                if ((r >> t) & 1) mine |= 1ull << g.q[t];
+            tile[threadIdx.x] = a[mine];
+        }
+        __syncthreads();
+        if (valid) {
+            const V *in = tile + (threadIdx.x & ~63u);
+            V acc = cmul(ldc<R>(m, (uint64_t)r * 64), in[0]);
+            for (int c = 1; c < 64; ++c) cmac(acc, ldc<R>(m, (uint64_t)r * 64 + c), in[c]);
+            a[mine] = acc;
+        }
+        __syncthreads();  // the tile is reused by the next groups
     }
 }
 
@@ -114,14 +127,16 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_diag(c2_t<R> *__restrict__ a, const c2_t<R> *__restrict__ T,
                                                  uint64_t len, DiagArgs d)
 {
-    const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * 2;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2; i0 < len; i0 += stride) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const uint64_t x = i0 + u;
-        if (x >= len) return;
-        uint32_t y = 0;
-        for (int t = 0; t < d.k; ++t) y |= (uint32_t)((x >> d.q[t]) & 1) << t;
-        a[x] = cmul(a[x], T[y]);
+        for (int u = 0; u < 2; ++u) {
+            const uint64_t x = i0 + u;
+            if (x >= len) return;
+            uint32_t y = 0;
+            for (int t = 0; t < d.k; ++t) y |= (uint32_t)((x >> d.q[t]) & 1) << t;
+            a[x] = cmul(a[x], T[y]);
+        }
     }
 }
 
@@ -130,11 +145,13 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_kron(c2_t<R> *__restrict__ dst, const c2_t<R> *__restrict__ lo,
                                                  const c2_t<R> *__restrict__ hi, int nlo, uint64_t len)
 {
-    const uint64_t x0 = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock * 4;
+    for (uint64_t x0 = (uint64_t)blockIdx.x * kBlock * 4 + threadIdx.x; x0 < len; x0 += stride) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const uint64_t x = x0 + (uint64_t)u * kBlock;
-        if (x < len) dst[x] = cmul(lo[x & ((1ull << nlo) - 1)], hi[x >> nlo]);
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t x = x0 + (uint64_t)u * kBlock;
+            if (x < len) dst[x] = cmul(lo[x & ((1ull << nlo) - 1)], hi[x >> nlo]);
+        }
     }
 }
 
@@ -149,11 +166,12 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_perm(c2_t<R> *__restrict__ dst, const c2_t<R> *__restrict__ src,
                                                  uint64_t len, PermArgs p)
 {
-    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (x >= len) return;
-    uint64_t y = 0;
-    for (int b = 0; b < p.n; ++b) y |= ((x >> b) & 1ull) << p.perm[b];
-    dst[y] = src[x];
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < len; x += stride) {
+        uint64_t y = 0;
+        for (int b = 0; b < p.n; ++b) y |= ((x >> b) & 1ull) << p.perm[b];
+        dst[y] = src[x];
+    }
 }
 
 // Qubit reordering in place (Sec. 2.3, Eq. of the swap gate): exchanges
@@ -166,6 +184,7 @@ struct SwapArgs {
     int32_t npairs, tbits;
     int32_t lo[6], hi[6];
     uint64_t tilemask, outmask;
+    uint64_t ntiles;
 };
 
 __device__ __forceinline__ uint32_t extract_bits(uint64_t x, uint64_t mask)
@@ -186,16 +205,19 @@ __global__ __launch_bounds__(kBlock) void k_swap_bits(c2_t<R> *__restrict__ a, S
     using V = c2_t<R>;
     extern __shared__ char smem_raw[];
     V *lds = reinterpret_cast<V *>(smem_raw);
-    const uint64_t base = deposit(blockIdx.x, S.outmask);
     const uint32_t ntile = 1u << S.tbits;
-    for (uint32_t i = threadIdx.x; i < ntile; i += kBlock) lds[i] = a[base | deposit(i, S.tilemask)];
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < ntile; i += kBlock) {
-        const uint64_t y = base | deposit(i, S.tilemask);
-        uint64_t x = y;
-        for (int k = 0; k < S.npairs; ++k)
-            if (((y >> S.lo[k]) ^ (y >> S.hi[k])) & 1ull) x ^= (1ull << S.lo[k]) | (1ull << S.hi[k]);
-        a[y] = lds[extract_bits(x, S.tilemask)];
+    for (uint64_t t = blockIdx.x; t < S.ntiles; t += gridDim.x) {  // uniform across the workgroup
+        const uint64_t base = deposit(t, S.outmask);
+        for (uint32_t i = threadIdx.x; i < ntile; i += kBlock) lds[i] = a[base | deposit(i, S.tilemask)];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < ntile; i += kBlock) {
+            const uint64_t y = base | deposit(i, S.tilemask);
+            uint64_t x = y;
+            for (int k = 0; k < S.npairs; ++k)
+                if (((y >> S.lo[k]) ^ (y >> S.hi[k])) & 1ull) x ^= (1ull << S.lo[k]) | (1ull << S.hi[k]);
+            a[y] = lds[extract_bits(x, S.tilemask)];
+        }
+        __syncthreads();  // the LDS tile is reused by the next tile
     }
 }
 
@@ -234,10 +256,11 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_gather(const c2_t<R> *__restrict__ a, const uint64_t *__restrict__ idx,
                                                    uint64_t m, double2 *__restrict__ out)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= m) return;
-    const c2_t<R> v = a[idx[i]];
-    out[i] = make_double2((double)v.x, (double)v.y);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const c2_t<R> v = a[idx[i]];
+        out[i] = make_double2((double)v.x, (double)v.y);
+    }
 }
 
 // Marginal probabilities, deterministic: one wave per (bin y, z segment) sums
@@ -582,11 +605,13 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
         marg_lane_shape(n, L.kh, &L.zseg, &L.nseg);
         nseg = L.nseg;
         const uint64_t waves = (1ull << L.kh) * L.nseg;
+        if (waves * 64 > kMaxBlocks * kBlock) return hipErrorInvalidValue;  // one wave per unit, no grid stride
         k_marg_partial_lanes<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, L, scratch);
     } else {
         marg_shape(n, nq, &M.zseg, &M.nseg);
         nseg = M.nseg;
         const uint64_t waves = nbins * M.nseg;
+        if (waves * 64 > kMaxBlocks * kBlock) return hipErrorInvalidValue;  // one wave per unit, no grid stride
         k_marg_partial<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, M, scratch);
     }
     if (nseg >= 64)
@@ -632,10 +657,9 @@ hipError_t launch_swap_bits(void *state, int n, const int *lo, const int *hi, in
     S.tilemask = tm;
     S.tbits = __builtin_popcountll(tm);
     S.outmask = ((n >= 64) ? ~0ull : ((1ull << n) - 1)) & ~tm;
-    const uint64_t blocks = 1ull << (n - S.tbits);
-    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    S.ntiles = 1ull << (n - S.tbits);
     const size_t lds = sizeof(c2_t<R>) << S.tbits;
-    k_swap_bits<R><<<(uint32_t)blocks, kBlock, lds, s>>>((c2_t<R> *)state, S);
+    k_swap_bits<R><<<blocks_for(S.ntiles, 1), kBlock, lds, s>>>((c2_t<R> *)state, S);
     return hipGetLastError();
 }
 

@@ -271,6 +271,10 @@ PAPER_BENCHMARKS = (
      {"paper_ms_per_gate": 1.26, "paper": "Table 2, QFT with the booster, one H100, per gate"}),
     ("rzz30", "30-qubit H layer + RZZ on all 435 pairs (gate-level benchmark)",
      {"paper_s": 0.02, "paper": "Table 1, all optimisations, 64 H100s (context only)"}),
+    ("rzz33", "33-qubit H layer + RZZ on all 528 pairs, a 128 GiB state",
+     {"paper_s": 0.04, "paper": "Table 1, all optimisations, 64 H100s (context only)"}),
+    ("rzz34", "34-qubit H layer + RZZ on all 561 pairs, a 256 GiB state",
+     {"paper_s": 0.07, "paper": "Table 1, all optimisations, 64 H100s (context only)"}),
 )
 
 
@@ -289,9 +293,20 @@ def describe(name, r, dtype):
 def paper_benchmarks(steps=3, warmup=1):
     from paper_2604_12256_amd import qsim
     rows = []
+    import torch
     for name, what, ref in PAPER_BENCHMARKS:
+        n = int(name[-2:])
+        free, _ = torch.cuda.mem_get_info()
+        if free < (16 << n) + (4 << 30):
+            log(f"[bench] {name}: skipped, {free / 2**30:.0f} GiB free")
+            continue
         log(f"[bench] {name}")
-        d = run_workload(name, "c128", qsim.OPT_ALL, steps, warmup, profile=False)
+        try:
+            d = run_workload(name, "c128", qsim.OPT_ALL, steps, warmup, profile=False)
+        except (torch.cuda.OutOfMemoryError, qsim.QsimError) as e:  # a state that does not fit this device
+            log(f"[bench] {name}: skipped ({type(e).__name__}: {str(e)[:120]})")
+            torch.cuda.empty_cache()
+            continue
         ms = d["wall_s"] / steps * 1e3
         hb = d["stats"]["algorithmic_bytes"] / (d["run_ms"] / 1e3) / 1e9
         row = {"workload": f"{name}: {what}, complex128, all passes", "ms_per_step": round(ms, 3),

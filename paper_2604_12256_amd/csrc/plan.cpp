@@ -9,7 +9,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 
 #include "ir.hpp"
 
@@ -1053,28 +1055,34 @@ struct Builder {
     {
         if ((o.opt & SIM_OPT_DIAG) && (o.opt & SIM_OPT_STAGES)) {
             const size_t mark = plan.ops.size();
-            const PlanStats saved = plan.stats;
-            const std::vector<int> saved_layout = plan.layout;
+            // the detector's lowering is built on a copy of the plan on a
+            // second thread while this one builds the plain lowering
+            Plan alt = plan;
             uint64_t v = 0;
-            std::vector<Operator> dd = diagonal_detector(nb, (int)o.D, gates, &v);
-            lower_gates(buffer, nb, std::move(dd));
-            double t_dd = 0;
-            for (size_t i = mark; i < plan.ops.size(); ++i) t_dd += est_seconds(plan.ops[i]);
-            std::vector<PlanOp> with_dd(std::make_move_iterator(plan.ops.begin() + mark),
-                                        std::make_move_iterator(plan.ops.end()));
-            plan.ops.resize(mark);
-            const PlanStats stats_dd = plan.stats;
-            const std::vector<int> layout_dd = plan.layout;
-            plan.stats = saved;
-            plan.layout = saved_layout;
-            lower_gates(buffer, nb, gates);
-            double t_plain = 0;
+            std::exception_ptr err;
+            std::thread th([&] {
+                try {
+                    Builder b2{alt, o};
+                    b2.lower_gates(buffer, nb, diagonal_detector(nb, (int)o.D, gates, &v));
+                } catch (...) {
+                    err = std::current_exception();
+                }
+            });
+            try {
+                lower_gates(buffer, nb, gates);
+            } catch (...) {
+                th.join();
+                throw;
+            }
+            th.join();
+            if (err) std::rethrow_exception(err);
+            double t_dd = 0, t_plain = 0;
+            for (size_t i = mark; i < alt.ops.size(); ++i) t_dd += est_seconds(alt.ops[i]);
             for (size_t i = mark; i < plan.ops.size(); ++i) t_plain += est_seconds(plan.ops[i]);
             if (t_dd <= t_plain) {  // a tie keeps the detector: fewer, wider table members
-                plan.ops.resize(mark);
-                for (PlanOp &op : with_dd) plan.ops.push_back(std::move(op));
-                plan.stats = stats_dd;
-                plan.layout = layout_dd;
+                plan.ops.swap(alt.ops);
+                plan.stats = alt.stats;
+                plan.layout = alt.layout;
             }
             plan.stats.dd_visits += v;
             return;

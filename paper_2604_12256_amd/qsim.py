@@ -295,6 +295,7 @@ class Simulator:
         if getattr(self, "_ctx", None):
             self._lib.sim_destroy(self._ctx)
             self._ctx = None
+        self.state = None  # the device state buffer may be released once the context is gone
 
     def __del__(self) -> None:
         try:

@@ -32,10 +32,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def need_free(bytes_needed):
+def need_free(bytes_needed, margin=8 << 30):
     import torch
     free, _ = torch.cuda.mem_get_info()
-    if free < bytes_needed + (8 << 30):
+    if free < bytes_needed + margin:
         pytest.skip(f"needs {bytes_needed / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
 
 
@@ -173,4 +173,21 @@ def test_34q_complex64_block_product(oracle_mod):
     got = sim.amplitudes(idx)
     want = block_product_amplitudes(oracle_mod, per_block, idx)
     assert np.max(np.abs(got - want)) <= 2e-5 * np.max(np.abs(want)) + 1e-9
+    release(sim)
+
+
+def test_34q_complex128_diagonal_closed_form():
+    """A 256 GiB complex128 state (most of the device): H on every qubit and
+    the fully-connected RZZ layer, against the diagonal closed form."""
+    from oracle import closed_forms as CF
+    n = 34
+    need_free(16 << n, margin=3 << 30)
+    gates = W.rzz_full(n, 7)
+    idx = W.sample_indices(n, 1 << 14, 35)
+    say(f"34q complex128 fully-connected RZZ: {len(gates)} gates")
+    sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    assert np.max(np.abs(sim.amplitudes(idx) - CF.hadamard_diagonal_amplitudes(n, gates, idx))) <= TOL128
+    np.testing.assert_allclose(sim.expect_z([0, 1 << 33]), [1, 0], atol=1e-12)
     release(sim)

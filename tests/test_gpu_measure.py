@@ -161,3 +161,23 @@ def test_measurement_errors():
         sim.expect_z([1 << n])
     assert sim.sample(np.array([])).size == 0
     sim.close()
+
+
+def test_measurement_smallest_registers(oracle_mod):
+    """One to three qubits: every outcome path, sampling at cell edges and
+    the all-qubit Z string."""
+    from oracle import measure as M
+    for n in (1, 2, 3):
+        gates = W.random_mixed(n, 10, seed=40 + n, max_k=n)
+        for dtype in ("c128", "c64"):
+            sim = run(n, gates, dtype)
+            state = sim.amplitudes().astype(np.complex128)
+            u = np.array([0.0, 0.25, 0.5, 0.75, 0.999999])
+            check_samples(sim.sample(u), M.sample(state, u), state, u)
+            full = (1 << n) - 1
+            np.testing.assert_allclose(sim.expect_z([0, full]), M.expect_z(state, [0, full]), atol=1e-12)
+            m_ref, p_ref, _ = M.measure(state, n - 1, 0.6)
+            m, p = sim.measure(n - 1, 0.6)
+            if abs(0.6 - (p_ref if m_ref == 0 else 1 - p_ref)) > 1e-9:
+                assert m == m_ref and abs(p - p_ref) < (1e-12 if dtype == "c128" else 1e-6)
+            sim.close()

@@ -309,18 +309,14 @@ struct Builder {
         Block Z;
         struct ZMember {
             const Operator *g;
-            uint32_t S;
-            std::vector<int> T;
+            uint32_t S;           // register bits
+            std::vector<int> T;   // selector qubits
+            uint64_t tmask;       // selector qubits as a mask
         };
         std::vector<ZMember> zmem;
         // a chunk reads the slice of a table its chunk bits select: at most
         // kZloc chunk-local table qubits keep that slice (16 KiB) in L1
         const int kZsel = 12, kZmax = 14, kZloc = c64 ? 11 : 10;
-        auto local_count = [&](uint32_t S, const std::vector<int> &T) {
-            int c = popc(S);
-            for (int x : T) c += (int)((local_phys >> x) & 1);
-            return c;
-        };
         auto member_sets = [&](const std::vector<ZMember> &ms, uint32_t *S, std::vector<int> *T) {
             *S = 0;
             T->clear();
@@ -330,17 +326,59 @@ struct Builder {
                     if (std::find(T->begin(), T->end(), x) == T->end()) T->push_back(x);
             }
         };
+        // Packs commuting diagonal members into as few tables as the caps
+        // allow (at most kZsel selectors, 2^kZmax entries, kZloc chunk-local
+        // qubits): a table starts from the widest unplaced member and grows
+        // by the member that adds the fewest new qubits, so gates inside the
+        // table's qubits join first.  Members commute, so order is free.
         auto emit_members = [&](std::vector<ZMember> &ms) {
-            if (ms.empty()) return;
-            uint32_t S;
-            std::vector<int> T;
-            member_sets(ms, &S, &T);
-            KOp k;
-            k.type = KOp::DIAG;
-            k.dq = qlist(S, T);
-            for (const ZMember &m : ms) k.members.push_back(*m.g);
-            *flops_per_amp += op_flops(true, 0);
-            ph.ops.push_back(std::move(k));
+            const size_t nm = ms.size();
+            std::vector<char> used(nm, 0);
+            size_t left = nm;
+            auto fits = [&](uint32_t S, uint64_t T) {
+                return popc(T) <= kZsel && popc(S) + popc(T) <= kZmax &&
+                       popc(S) + popc(T & local_phys) <= kZloc;
+            };
+            while (left) {
+                size_t seed = nm;
+                for (size_t i = 0; i < nm; ++i)
+                    if (!used[i] && (seed == nm || popc(ms[i].S) + popc(ms[i].tmask) >
+                                                       popc(ms[seed].S) + popc(ms[seed].tmask)))
+                        seed = i;
+                uint32_t S = ms[seed].S;
+                uint64_t T = ms[seed].tmask;
+                std::vector<size_t> grp{seed};
+                used[seed] = 1;
+                --left;
+                while (left) {
+                    size_t best = nm;
+                    int best_add = 1 << 30;
+                    for (size_t i = 0; i < nm && best_add > 0; ++i) {
+                        if (used[i]) continue;
+                        const int add = popc(ms[i].S & ~S) + popc(ms[i].tmask & ~T);
+                        if (add < best_add && fits(S | ms[i].S, T | ms[i].tmask)) {
+                            best = i;
+                            best_add = add;
+                        }
+                    }
+                    if (best == nm) break;
+                    S |= ms[best].S;
+                    T |= ms[best].tmask;
+                    used[best] = 1;
+                    --left;
+                    grp.push_back(best);
+                }
+                std::sort(grp.begin(), grp.end());
+                std::vector<int> tl;
+                for (int q = 0; q < 64; ++q)
+                    if ((T >> q) & 1) tl.push_back(q);
+                KOp k;
+                k.type = KOp::DIAG;
+                k.dq = qlist(S, tl);
+                for (size_t i : grp) k.members.push_back(*ms[i].g);
+                *flops_per_amp += op_flops(true, 0);
+                ph.ops.push_back(std::move(k));
+            }
             ms.clear();
         };
         auto emit_z = [&]() {
@@ -348,20 +386,14 @@ struct Builder {
             Z = Block();
         };
         auto z_add = [&](const Operator &g, uint32_t gS, const std::vector<int> &gT) {
-            std::vector<int> T2 = Z.T;
-            for (int x : gT)
-                if (std::find(T2.begin(), T2.end(), x) == T2.end()) T2.push_back(x);
-            uint32_t S2 = Z.S | gS;
-            if (Z.open && ((int)T2.size() > kZsel || popc(S2) + (int)T2.size() > kZmax ||
-                           local_count(S2, T2) > kZloc)) {
-                emit_z();
-                T2 = gT;
-                S2 = gS;
+            uint64_t tm = 0;
+            for (int x : gT) {
+                tm |= 1ull << x;
+                if (std::find(Z.T.begin(), Z.T.end(), x) == Z.T.end()) Z.T.push_back(x);
             }
             Z.open = true;
-            Z.S = S2;
-            Z.T = T2;
-            zmem.push_back({&g, gS, gT});
+            Z.S |= gS;
+            zmem.push_back({&g, gS, gT, tm});
         };
         // the members of Z on any of the register bits `bits` leave Z (a dense
         // gate on those bits follows them; the rest of Z commutes with it)
@@ -435,7 +467,11 @@ struct Builder {
                             if (((gS >> b) & 1) && reg_phys[b] == t) clash = true;
                 }
                 if (!clash && sel_ok && fused <= B.indiv + gcost + 1e-9) {
-                    emit_members(P);  // they commute with B's earlier gates
+                    if (!P.empty()) {  // the whole table goes first, packed (it commutes with every open block)
+                        for (ZMember &m : P) zmem.push_back(std::move(m));
+                        P.clear();
+                        emit_z();
+                    }
                     std::vector<int> l2 = qlist(S2, T2);
                     if (l2 != B.acc.q) B.acc = embed(B.acc, l2);
                     apply_left(B.acc, g);
@@ -488,8 +524,10 @@ struct Builder {
                     nb.S = S2;
                     nb.T = T2;
                     P.clear();
-                } else {
-                    emit_members(P);
+                } else {  // the whole table goes first, packed
+                    for (ZMember &m : P) zmem.push_back(std::move(m));
+                    P.clear();
+                    emit_z();
                     nb.acc = embed(g, qlist(gS, gT));
                 }
             } else {

@@ -267,6 +267,9 @@ PAPER_BENCHMARKS = (
     ("qaoa30", "30-qubit 5-level fully-connected QAOA (H, then per level RZZ on all 435 pairs and RX on "
                "every qubit), 2355 gates",
      {"paper_s": 0.99, "paper": "Table 3, all optimisations, one H100"}),
+    ("qaoa31", "31-qubit 5-level fully-connected QAOA (RZZ on all 465 pairs and RX on every qubit per level), "
+               "2511 gates",
+     {"paper_ms_per_gate": 2.35, "paper": "Table 2, QAOA with the booster, one H100, per gate"}),
     ("qft31", "31-qubit QFT of a seeded basis state (X prep, H + 465 controlled phases, 15 closing SWAPs)",
      {"paper_ms_per_gate": 1.26, "paper": "Table 2, QFT with the booster, one H100, per gate"}),
     ("rzz30", "30-qubit H layer + RZZ on all 435 pairs (gate-level benchmark)",

@@ -93,6 +93,9 @@ typedef struct {
     uint32_t B;            /* booster division parameter (0 = default 4) */
     uint32_t force_fuse_k; /* >0: fusion-only plans fuse greedily to this many qubits
                               regardless of cost (exercises the MFMA path) */
+    uint32_t L;            /* lowest physical qubits every stage keeps local, 1..6 (0 = default:
+                              one 128-byte cache line per contiguous run, 3 for C128, 4 for C64) */
+    uint32_t reserved;     /* 0 */
     void *dev_state;           /* device buffer, >= 2^N * 16 B (C128) or 8 B (C64) */
     uint64_t dev_state_bytes;
     void *stream;              /* hipStream_t the context launches on (NULL = default) */

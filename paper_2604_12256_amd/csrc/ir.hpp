@@ -105,7 +105,7 @@ struct PlanStats {
 struct Options {
     uint32_t opt = 0, C = 0, F = 5, D = 10, B = 4, force_fuse_k = 0;
     int reg_bits = 4;                 // register bits per thread in a stage
-    int fixed_low = 6;                // physical bits every stage keeps local (coalescing)
+    int fixed_low = 6;                // physical bits every stage keeps local (coalescing; set per dtype)
 };
 
 struct Plan {

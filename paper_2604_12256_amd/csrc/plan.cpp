@@ -87,6 +87,13 @@ Options resolve_options(const sim_options *o, sim_dtype dtype, int n)
         r.force_fuse_k = o->force_fuse_k;
     }
     r.reg_bits = dtype == SIM_C128 ? 4 : 5;
+    // Every stage keeps the lowest physical qubits local so that a wave's
+    // loads and stores come in contiguous runs of whole 128-byte cache lines:
+    // 8 complex128 or 16 complex64 amplitudes.  Fewer fixed qubits leave more
+    // room in the local set (on the 30-qubit layered circuit 15 passes
+    // instead of 21 with six fixed qubits, measured 9% faster on MI355X);
+    // runs of half a line measured slower.
+    r.fixed_low = (o && o->L) ? (int)std::min<uint32_t>(o->L, 6) : (dtype == SIM_C128 ? 3 : 4);
     // Default chunk: 2^12 complex128 / 2^13 complex64 amplitudes (64 KiB), so two
     // workgroups share a CU and one's HBM load/store overlaps the other's compute.
     if (r.C == 0) r.C = dtype == SIM_C128 ? 12 : 13;
@@ -879,8 +886,10 @@ struct Builder {
                 if ((nd >> q) & 1) freq[q] += 1.0;
         }
         std::vector<int> lows, highs;
+        // the in-place permutation pass exchanges bits below 6 with bits at 6
+        // or above (its tile holds the low six bits and the partners)
         for (int q = 0; q < low; ++q) lows.push_back(q);
-        for (int q = low; q < nb; ++q) highs.push_back(q);
+        for (int q = std::max(low, 6); q < nb; ++q) highs.push_back(q);
         std::stable_sort(lows.begin(), lows.end(), [&](int a, int b) { return freq[a] < freq[b]; });
         std::stable_sort(highs.begin(), highs.end(), [&](int a, int b) { return freq[a] > freq[b]; });
         std::vector<int> sigma(nb);
@@ -1149,7 +1158,8 @@ struct Builder {
             plan.ops.push_back(std::move(st));
             return;
         }
-        if ((o.opt & SIM_OPT_STAGES) && nb >= o.fixed_low + o.reg_bits) {
+        // a stage chunk holds at least one wave (64 threads of 2^reg_bits amplitudes)
+        if ((o.opt & SIM_OPT_STAGES) && nb >= 6 + o.reg_bits) {
             stages(buffer, nb, gates);
         } else if (o.opt & SIM_OPT_FUSE) {
             fused_passes(buffer, nb, gates);

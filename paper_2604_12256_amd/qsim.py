@@ -37,7 +37,7 @@ class SimGate(ctypes.Structure):
 class SimOptions(ctypes.Structure):
     _fields_ = [("opt", ctypes.c_uint32), ("C", ctypes.c_uint32), ("F", ctypes.c_uint32),
                 ("D", ctypes.c_uint32), ("B", ctypes.c_uint32), ("force_fuse_k", ctypes.c_uint32),
-                ("dev_state", ctypes.c_void_p), ("dev_state_bytes", ctypes.c_uint64),
+                ("L", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("dev_state", ctypes.c_void_p), ("dev_state_bytes", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -164,9 +164,9 @@ def _as_gates(gates) -> _Gates:
 
 
 def _options(opt: int, C: int, F: int, D: int, B: int, force_fuse_k: int, state_ptr: int = 0,
-             state_bytes: int = 0, stream: int = 0) -> SimOptions:
+             state_bytes: int = 0, stream: int = 0, L: int = 0) -> SimOptions:
     o = SimOptions()
-    o.opt, o.C, o.F, o.D, o.B, o.force_fuse_k = opt, C, F, D, B, force_fuse_k
+    o.opt, o.C, o.F, o.D, o.B, o.force_fuse_k, o.L = opt, C, F, D, B, force_fuse_k, L
     o.dev_state = state_ptr or None
     o.dev_state_bytes = state_bytes
     o.stream = stream or None
@@ -177,7 +177,7 @@ class Simulator:
     """One state vector on the GPU and the circuit loaded into it."""
 
     def __init__(self, n: int, dtype: str = "c128", opt: int = 0, C: int = 0, F: int = 0, D: int = 0,
-                 B: int = 0, force_fuse_k: int = 0, state=None, stream=None, device: int = 0) -> None:
+                 B: int = 0, force_fuse_k: int = 0, state=None, stream=None, device: int = 0, L: int = 0) -> None:
         import torch
         self._lib = load_library()
         if not torch.cuda.is_available():
@@ -190,7 +190,7 @@ class Simulator:
         self.state = state
         self.stream = stream if stream is not None else torch.cuda.current_stream(state.device)
         o = _options(opt, C, F, D, B, force_fuse_k, state.data_ptr(), state.numel() * state.element_size(),
-                     self.stream.cuda_stream)
+                     self.stream.cuda_stream, L)
         ctx = ctypes.c_void_p()
         st = self._lib.sim_create(self.n, DTYPES[dtype], ctypes.byref(o), ctypes.byref(ctx))
         if st != OK:
@@ -329,11 +329,11 @@ class Plan:
     """The execution plan the library builds for a circuit (no GPU needed)."""
 
     def __init__(self, n: int, gates: Sequence, dtype: str = "c128", opt: int = OPT_ALL, C: int = 0,
-                 F: int = 0, D: int = 0, B: int = 0, force_fuse_k: int = 0) -> None:
+                 F: int = 0, D: int = 0, B: int = 0, force_fuse_k: int = 0, L: int = 0) -> None:
         self._lib = load_library()
         self.n = n
         m = _as_gates(gates)
-        o = _options(opt, C, F, D, B, force_fuse_k)
+        o = _options(opt, C, F, D, B, force_fuse_k, L=L)
         p = ctypes.c_void_p()
         st = self._lib.sim_plan_build(n, DTYPES[dtype], ctypes.byref(o), m.arr, m.n, ctypes.byref(p))
         if st != OK:

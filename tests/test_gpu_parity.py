@@ -68,6 +68,23 @@ def test_random_circuits_every_pass(oracle_mod, opt):
         check128(got, oracle_mod.run(n, gates), f"n={n} opt={opt}")
 
 
+@pytest.mark.parametrize("L", [1, 3, 4, 6])
+def test_stage_kernel_fixed_low_qubits(oracle_mod, L):
+    """Stages whose local set holds only L of the low qubits (lanes on high
+    qubits, contiguous runs of 2^L amplitudes), both dtypes."""
+    n = 17
+    gates = W.layered(n, 6, seed=20 + L)
+    want = oracle_mod.run(n, gates)
+    for dtype in ("c128", "c64"):
+        say(f"fixed low L={L} {dtype}")
+        got, st = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_ALL, L=L)
+        assert st["n_stages"] >= 2
+        if dtype == "c128":
+            check128(got, want, f"L={L}")
+        else:
+            check64(got, want, oracle_mod, f"L={L}")
+
+
 @pytest.mark.parametrize("C", [10, 11, 12, 13])
 def test_stage_kernel_chunk_sizes(oracle_mod, C):
     """Targets on register, lane, wave and global bits for every chunk size."""
@@ -141,7 +158,7 @@ def test_qubit_reordering_permutation(oracle_mod):
     for n, C in ((14, 10), (18, 12)):
         gates = high_qubit_circuit(n, 6, 2, 12, 5)
         want = oracle_mod.run(n, gates)
-        sim = qsim.Simulator(n, opt=qsim.OPT_ALL, C=C)
+        sim = qsim.Simulator(n, opt=qsim.OPT_ALL, C=C, L=6)   # six idle fixed low qubits
         sim.load(gates)
         sim.run()
         st = sim.stats()

@@ -271,7 +271,8 @@ def high_qubit_circuit(n, offset, layers_lo, layers_hi, seed):
 def test_remap_emits_permutation_and_matches_oracle(oracle_mod):
     n = 14
     gates = high_qubit_circuit(n, 6, 2, 12, 5)
-    p = qsim.Plan(n, gates, opt=qsim.OPT_ALL, C=10)
+    # six fixed low qubits idle while the work sits on the top ones
+    p = qsim.Plan(n, gates, opt=qsim.OPT_ALL, C=10, L=6)
     ops = p.ops()
     perms = [o for o in ops if o["kind"] == "PERM"]
     assert perms, "expected a qubit permutation"
@@ -284,7 +285,7 @@ def test_remap_emits_permutation_and_matches_oracle(oracle_mod):
     want = oracle_mod.run(n, gates)
     assert np.max(np.abs(run_plan(ops, n, p.layout()) - want)) < 1e-12
     # fewer full passes than without reordering
-    q = qsim.Plan(n, gates, opt=qsim.OPT_ALL & ~qsim.OPT_REMAP, C=10)
+    q = qsim.Plan(n, gates, opt=qsim.OPT_ALL & ~qsim.OPT_REMAP, C=10, L=6)
     assert p.stats()["full_passes"] < q.stats()["full_passes"]
 
 
@@ -293,10 +294,10 @@ def test_remap_free_relabel_at_start():
     n = 30
     gates = [Gate(x.kind, tuple(q + 10 for q in x.qubits), x.theta, x.data) for x in W.layered(20, 10, 3)]
     opt = qsim.OPT_STAGES | qsim.OPT_FUSE | qsim.OPT_REMAP
-    p = qsim.Plan(n, gates, opt=opt)
+    p = qsim.Plan(n, gates, opt=opt, L=6)   # six fixed low qubits, all idle
     assert not [o for o in p.ops() if o["kind"] == "PERM"]
     assert p.layout() != list(range(n))
-    q = qsim.Plan(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE)
+    q = qsim.Plan(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE, L=6)
     assert p.stats()["full_passes"] < q.stats()["full_passes"]
 
 
@@ -421,3 +422,21 @@ def test_phase_diagonals_merge_into_wide_tables(oracle_mod):
             for use_k in (True, False):
                 got = run_plan(ops, n, p.layout(), use_kernel_ops=use_k)
                 assert np.max(np.abs(got - want)) < 1e-12, (dtype, C, use_k)
+
+
+@pytest.mark.parametrize("L", [1, 3, 4, 6])
+def test_fixed_low_qubits_option(oracle_mod, L):
+    """Every choice of always-local low qubits gives the oracle's state, and
+    fewer fixed qubits never need more stage passes here."""
+    n = 13
+    gates = W.layered(n, 6, seed=L)
+    want = oracle_mod.run(n, gates)
+    p = qsim.Plan(n, gates, opt=qsim.OPT_ALL, C=10, L=L)
+    ops = p.ops()
+    for o in ops:
+        if o["kind"] == "STAGE" and o["buffer"] == 0:
+            assert set(range(L)) <= set(o["local"])
+    assert np.max(np.abs(run_plan(ops, n, p.layout()) - want)) < 1e-12
+    assert np.max(np.abs(run_plan(ops, n, p.layout(), use_kernel_ops=False) - want)) < 1e-12
+    if L < 6:
+        assert p.stats()["full_passes"] <= qsim.Plan(n, gates, opt=qsim.OPT_ALL, C=10, L=6).stats()["full_passes"]

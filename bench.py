@@ -336,7 +336,7 @@ def main():
                     help="print a per-kernel time / HBM-rate table at 30 qubits instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the state vector is not sharded across "
+        print("bench.py: this simulator runs on one GPU only (the state vector is not sharded across "
               "GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     from paper_2604_12256_amd import qsim

@@ -44,7 +44,7 @@ typedef enum {
     SIM_E_NOMEM = 2,       /* a device or host buffer is too small / allocation failed */
     SIM_E_DEVICE = 3,      /* a HIP runtime error; text from sim_last_error */
     SIM_E_STATE = 4,       /* call out of order (e.g. outputs before sim_run) */
-    SIM_E_UNSUPPORTED = 5  /* valid request outside what this build implements */
+    SIM_E_UNSUPPORTED = 5  /* valid request outside what the library implements */
 } sim_status;
 
 typedef enum { SIM_C128 = 0, SIM_C64 = 1 } sim_dtype;

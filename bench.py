@@ -386,7 +386,7 @@ def main():
                             "gate_apps_per_s": round(d["gates"] / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
                             "hbm_GBps": round(dh, 1), "hbm_frac": round(dh / HBM_PEAK_GBS, 4),
                             "full_passes": d["stats"]["full_passes"],
-                            "roofline": roofline(d["per_kind"], "c128", 3)}
+                            "roofline": roofline(d["per_kind"], "c128", 3, "diag30")}
         out["paper_benchmarks"] = paper_benchmarks()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -182,11 +182,19 @@ def test_small_and_degenerate(oracle_mod):
         for opt in (0, qsim.OPT_ALL):
             got, _ = gpu_state(n, gates, opt=opt)
             check128(got, oracle_mod.run(n, gates), f"n={n}")
-    # empty circuit: |0...0>
-    got, _ = gpu_state(12, [], opt=qsim.OPT_ALL)
-    want = np.zeros(1 << 12, dtype=np.complex128)
-    want[0] = 1
-    assert np.array_equal(got, want)
+    # empty circuit: |0...0>, in both precisions, planned and plain
+    for n in (1, 12):
+        want = np.zeros(1 << n, dtype=np.complex128)
+        want[0] = 1
+        for dtype in ("c128", "c64"):
+            for opt in (0, qsim.OPT_ALL):
+                got, _ = gpu_state(n, [], dtype=dtype, opt=opt)
+                assert np.array_equal(got, want), f"empty n={n} {dtype} opt={opt}"
+    # one qubit in complex64
+    gates = W.random_mixed(1, 40, seed=1, max_k=1)
+    for opt in (0, qsim.OPT_ALL):
+        got, _ = gpu_state(1, gates, dtype="c64", opt=opt)
+        check64(got, oracle_mod.run(1, gates), oracle_mod, f"n=1 c64 opt={opt}")
 
 
 def test_outputs_probabilities_norm_inner(oracle_mod):

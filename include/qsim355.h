@@ -120,13 +120,17 @@ typedef struct {
     double est_ms;             /* device time of the plan predicted by the optimiser's cost model */
 } sim_run_stats;
 
-/* Create a context for an n_qubits state of the given dtype.
+/* Create a context for an n_qubits state of the given dtype (the N-qubit
+ * state of Sec. 2.1: 2^N complex amplitudes, qubit j = bit j of the index).
  * opts->dev_state must hold 2^n amplitudes (SIM_E_NOMEM otherwise).
  * n_qubits: 1..34.  *out receives the context (caller frees with sim_destroy). */
 sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts, sim_ctx **out);
 
-/* Validate and deep-copy the circuit, then build the execution plan with the
- * context's options (host only; no device work except uploading tables).
+/* Validate and deep-copy the circuit (gates as defined in Sec. 2.2), then
+ * build the execution plan with the context's options: the optimiser of
+ * Sec. 4 (gate block search of Sec. 4.2 with limits C and F, merge booster
+ * Sec. 4.4, diagonal detector Sec. 4.5) choosing among the simulation
+ * schemes of Sec. 2.4.  Host only; no device work except uploading tables.
  * On error the previously loaded circuit stays in place. */
 sim_status sim_load_circuit(sim_ctx *ctx, const sim_gate *gates, uint64_t n_gates);
 
@@ -138,12 +142,16 @@ sim_status sim_run(sim_ctx *ctx);
  * state may be read only after the stream has been synchronised. */
 sim_status sim_run_async(sim_ctx *ctx);
 
-/* Copy amplitudes to host: out[2*i], out[2*i+1] = re, im of amplitude
+/* Copy amplitudes to host (the simulation result of Sec. 2.4: all amplitudes
+ * of the final state): out[2*i], out[2*i+1] = re, im of amplitude
  * idx[i] (logical index).  idx == NULL copies all 2^N amplitudes (n must then
  * be 2^N).  Synchronises the stream.  Requires a completed sim_run. */
 sim_status sim_amplitudes(sim_ctx *ctx, const uint64_t *idx, uint64_t n, double *out);
 
-/* Marginal probabilities over the qubit list (Sec. 2.3 measurement model):
+/* Marginal probabilities over the qubit list (the paper's measurement
+ * background in Sec. 2, an unnumbered subsection between Sec. 2.3 and
+ * Sec. 2.4: the probability of an outcome is the squared norm of the
+ * amplitudes the projector keeps):
  * out[y] = sum over i whose bit qubits[t] equals bit t of y of |a_i|^2,
  * accumulated in FP64 in a fixed order (deterministic).  nq = 0 gives the
  * norm in out[0].  nq <= 16.  out holds 2^nq doubles (host). */
@@ -208,6 +216,13 @@ typedef struct {
 /* Timings of the last profiled run, one entry per plan op (waits for the
  * stream).  cap = room in out; *n receives the number of plan ops. */
 sim_status sim_op_timings(sim_ctx *ctx, sim_op_timing *out, uint64_t cap, uint64_t *n);
+
+/* Device memory the context itself holds, in bytes, beside the caller-owned
+ * state: booster sub-states, operator tables, stage programs, small-circuit
+ * descriptors and reduction scratch (admission control of the serving loop
+ * counts it with the state).  Grows with sim_load_circuit and with output
+ * calls that need scratch; released by sim_destroy. */
+sim_status sim_device_bytes(const sim_ctx *ctx, uint64_t *out);
 
 /* Text of the last error on this context (static storage; never NULL). */
 const char *sim_last_error(const sim_ctx *ctx);

@@ -255,9 +255,13 @@ void og_inner(int n, const double *a, const double *b, double *out)
 }
 
 /*
- * Marginal distribution over the qubit list S (Sec. 2.3 measurement model):
+ * Marginal distribution over the qubit list S (the measurement background of
+ * Sec. 2, an unnumbered subsection between Sec. 2.3 and Sec. 2.4):
  * P[y] = sum over x with bit S[t] of x equal to bit t of y of |a_x|^2.
- * Per-thread bins over a static split, combined in thread order.
+ * The index range is cut into a fixed number of equal parts (independent of
+ * the thread count), each summed into its own bins in index order, and the
+ * parts are combined in part order: the result does not depend on
+ * OMP_NUM_THREADS.
  */
 int og_marginal(int n, const double *a, const int32_t *S, int ns, double *out)
 {
@@ -267,14 +271,14 @@ int og_marginal(int n, const double *a, const int32_t *S, int ns, double *out)
         for (int u = 0; u < t; ++u) if (S[u] == S[t]) return -1;
     }
     int64_t nb = (int64_t)1 << ns, len = (int64_t)1 << n;
-    int nth = omp_get_max_threads();
-    double *bins = (double *)calloc((size_t)nth * nb, sizeof(double));
+    int64_t parts = ns <= 20 ? 16 : 1;
+    if (parts > len) parts = len;
+    double *bins = (double *)calloc((size_t)(parts * nb), sizeof(double));
     if (!bins) return -1;
-#pragma omp parallel num_threads(nth)
-    {
-        int tid = omp_get_thread_num(), T = omp_get_num_threads();
-        int64_t lo = len * tid / T, hi = len * (tid + 1) / T;
-        double *mine = bins + (int64_t)tid * nb;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < parts; ++p) {
+        int64_t lo = len * p / parts, hi = len * (p + 1) / parts;
+        double *mine = bins + p * nb;
         for (int64_t x = lo; x < hi; ++x) {
             int64_t y = 0;
             for (int t = 0; t < ns; ++t) y |= (int64_t)((x >> S[t]) & 1) << t;
@@ -283,7 +287,7 @@ int og_marginal(int n, const double *a, const int32_t *S, int ns, double *out)
     }
     for (int64_t y = 0; y < nb; ++y) {
         double s = 0.0;
-        for (int t = 0; t < nth; ++t) s += bins[(int64_t)t * nb + y];
+        for (int64_t p = 0; p < parts; ++p) s += bins[p * nb + y];
         out[y] = s;
     }
     free(bins);

@@ -1016,6 +1016,16 @@ sim_status sim_op_timings(sim_ctx *c, sim_op_timing *out, uint64_t cap, uint64_t
 
 const char *sim_last_error(const sim_ctx *c) { return c ? c->err.c_str() : kNullCtx; }
 
+sim_status sim_device_bytes(const sim_ctx *c, uint64_t *out)
+{
+    if (!c || !out) return SIM_E_INVAL;
+    uint64_t total = 0;
+    for (const DevBuf *b : {&c->tables, &c->prog, &c->gdesc, &c->items, &c->scratch, &c->io}) total += b->bytes;
+    for (const DevBuf &b : c->subbufs) total += b.bytes;
+    *out = total;
+    return SIM_OK;
+}
+
 sim_status sim_destroy(sim_ctx *c)
 {
     if (!c) return SIM_E_INVAL;

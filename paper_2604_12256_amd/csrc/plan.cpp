@@ -106,17 +106,24 @@ Options resolve_options(const sim_options *o, sim_dtype dtype, int n)
 }
 
 // ---------------------------------------------------------------------------
-// Merge booster, divide component (Alg. 6): halve N (floor half first, then the
-// ceiling half) until a part is at most div_size; leaves are queued in order.
+// Merge booster, divide component (Alg. 6).  The division is a binary
+// halving of the qubit count: a part larger than div_size splits into its
+// floor half and its ceiling half, in that order, and the parts that need no
+// split are the leaves, listed left to right.  An explicit work list (next
+// part at the back) yields them in that order.
 void divider(int n, int div_size, std::vector<int> &que)
 {
-    if (n <= div_size) {
-        que.push_back(n);
-        return;
+    std::vector<int> todo{n};
+    while (!todo.empty()) {
+        const int part = todo.back();
+        todo.pop_back();
+        if (part <= div_size || part < 2) {
+            que.push_back(part);
+            continue;
+        }
+        todo.push_back(part - part / 2);  // ceiling half: visited second
+        todo.push_back(part / 2);         // floor half: visited first
     }
-    divider(n >> 1, div_size, que);
-    int m = (n & 1) ? n + 1 : n;
-    divider(m >> 1, div_size, que);
 }
 
 // ---------------------------------------------------------------------------

@@ -101,6 +101,7 @@ def load_library() -> ctypes.CDLL:
         "sim_set_profiling": (I, [P, U32]),
         "sim_op_timings": (I, [P, ctypes.POINTER(SimOpTiming), U64, ctypes.POINTER(U64)]),
         "sim_last_error": (ctypes.c_char_p, [P]),
+        "sim_device_bytes": (I, [P, ctypes.POINTER(U64)]),
         "sim_destroy": (I, [P]),
         "sim_run_batch": (I, [P, U32, P]),
         "sim_plan_build": (I, [U32, I, ctypes.POINTER(SimOptions), ctypes.POINTER(SimGate), U64,
@@ -282,6 +283,12 @@ class Simulator:
 
     def set_profiling(self, enable: bool) -> None:
         self._check(self._lib.sim_set_profiling(self._ctx, 1 if enable else 0))
+
+    def device_bytes(self) -> int:
+        """Device memory the context holds beside the state buffer."""
+        v = ctypes.c_uint64()
+        self._check(self._lib.sim_device_bytes(self._ctx, ctypes.byref(v)))
+        return int(v.value)
 
     def op_timings(self) -> List[dict]:
         n = ctypes.c_uint64()

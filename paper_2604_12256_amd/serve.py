@@ -2,11 +2,18 @@
 
 Requests (circuits of 10..30 qubits) arrive over time.  The server
 
-* admits a request as soon as its state vector fits in the HBM budget
-  (state bytes = 2^n x 16 B for complex128, 8 B for complex64) and a slot is
-  free, in arrival order (a request that does not fit yet waits; smaller
-  later requests may pass it only if they fit — no starvation: a blocked head
-  request stops admission after `max_bypass` bypasses);
+* admits a request as soon as its device memory fits in the HBM budget and
+  a slot is free, in arrival order.  The memory of a request is its state
+  vector (2^n x 16 B for complex128, 8 B for complex64) plus the buffers its
+  context holds (booster sub-states, operator tables, stage programs,
+  descriptors): a reserve at admission, replaced by the context's own count
+  once the circuit is planned.  A request that does not fit yet waits at the
+  head of the queue; a later request may pass it if it fits.  Passing counts
+  as a bypass only when the later request takes what the head waits for (a
+  stream, or memory the head needs); after `max_bypass` bypasses such
+  requests wait behind the head (no starvation), while requests that take
+  nothing the head needs (small circuits while the head waits for a stream)
+  are still admitted;
 * runs every admitted large circuit on a stream of its own (plan on the
   host, then the optimised plan on the device), overlapping on the GPU;
 * collects admitted small circuits (whole state fits one workgroup's LDS)
@@ -60,6 +67,18 @@ def state_bytes(n: int, dtype: str) -> int:
     return AMP_BYTES[dtype] << n
 
 
+def is_small(n: int, dtype: str) -> bool:
+    return n <= SMALL_MAX[dtype]
+
+
+def reserve_bytes(n: int, dtype: str) -> int:
+    """Device memory reserved for a request at admission: its state and an
+    allowance for its context's own buffers (tables, programs, sub-states),
+    which the context's own count replaces once the circuit is planned."""
+    extra = (1 << 20) if is_small(n, dtype) else (64 << 20)
+    return state_bytes(n, dtype) + extra
+
+
 # ------------------------------------------------------------------ backends
 class GpuBackend:
     """Runs requests through the HIP library (one Simulator per request)."""
@@ -110,6 +129,10 @@ class GpuBackend:
     def done(self, token) -> bool:
         return token.query()
 
+    def held_bytes(self, sim) -> int:
+        """Device bytes the request's context holds beside its state."""
+        return sim.device_bytes()
+
     def release(self, rid: int, sim) -> None:
         if self.keep_states:
             self.kept[rid] = sim.amplitudes()
@@ -132,6 +155,12 @@ class _Slot:
     handle: object
     token: object = None
     stream_idx: Optional[int] = None
+    nbytes: int = 0                    # device memory it holds (state + context buffers)
+
+
+def held_bytes(backend, handle) -> int:
+    f = getattr(backend, "held_bytes", None)
+    return int(f(handle)) if f else 0
 
 
 def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypass: int = 8,
@@ -157,21 +186,33 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
             queue.append(pending[nxt])
             nxt += 1
         progressed = False
-        # admission in arrival order, by state memory
+        # admission in arrival order, by device memory
         i = 0
+        head_mem = head_stream = False   # what a blocked head request waits for
         while i < len(queue):
             req = queue[i]
-            small = req.n <= SMALL_MAX[req.dtype]
-            need = state_bytes(req.n, req.dtype)
-            fits = used + need <= budget and (small or free_streams)
-            if not fits:
-                if i == 0:
-                    bypassed += 1
-                    if bypassed > max_bypass:
-                        break          # hold the line for the head request
+            small = is_small(req.n, req.dtype)
+            need = reserve_bytes(req.n, req.dtype)
+            mem_ok = used + need <= budget
+            stream_ok = small or bool(free_streams)
+            if i == 0 and not (mem_ok and stream_ok):
+                head_mem, head_stream = not mem_ok, not stream_ok
                 i += 1
                 continue
-            if i == 0:
+            if not (mem_ok and stream_ok):
+                i += 1
+                continue
+            if i > 0:
+                # passing the blocked head: a bypass if it takes what the head waits for
+                head = queue[0]
+                takes = (head_stream and not small) or head_mem or \
+                    used + need + reserve_bytes(head.n, head.dtype) > budget
+                if takes:
+                    if bypassed >= max_bypass:
+                        i += 1         # hold the line for the head request
+                        continue
+                    bypassed += 1
+            else:
                 bypassed = 0
             queue.pop(i)
             used += need
@@ -183,8 +224,12 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
             else:
                 si = free_streams.pop(0)
                 slot = _Slot(req, backend.prepare(req, si), stream_idx=si)
+            # the context's own count replaces the admission reserve
+            slot.nbytes = state_bytes(req.n, req.dtype) + held_bytes(backend, slot.handle)
+            used += slot.nbytes - need
+            if not small:
                 res.start = backend.now()
-                slot.token = backend.start_stream(slot.handle, si)
+                slot.token = backend.start_stream(slot.handle, slot.stream_idx)
                 res.mode = "stream"
                 running.append(slot)
             progressed = True
@@ -203,7 +248,7 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
                 t = backend.now()
                 results[slot.req.rid].done = t
                 backend.release(slot.req.rid, slot.handle)
-                used -= state_bytes(slot.req.n, slot.req.dtype)
+                used -= slot.nbytes
                 free_streams.append(slot.stream_idx)
                 running.remove(slot)
                 n_done += 1
@@ -215,7 +260,7 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
             for s in batch:
                 results[s.req.rid].done = t
                 backend.release(s.req.rid, s.handle)
-                used -= state_bytes(s.req.n, s.req.dtype)
+                used -= s.nbytes
                 n_done += 1
                 if progress:
                     progress(n_done, len(pending))

@@ -297,6 +297,23 @@ def test_marginal_norm_inner_against_numpy(oracle_mod):
     assert oracle_mod.marginal(psi, [])[0] == pytest.approx(1.0, abs=1e-13)
 
 
+def test_marginal_independent_of_thread_count(oracle_mod):
+    """The oracle's marginals are bitwise the same for any OpenMP thread
+    count (fixed parts combined in a fixed order)."""
+    n = 14
+    psi = oracle_mod.run(n, W.random_mixed(n, 60, seed=21, max_k=2))
+    before = oracle_mod.num_threads()
+    outs = []
+    try:
+        for t in (1, 3, 8):
+            oracle_mod.set_threads(t)
+            outs.append(oracle_mod.marginal(psi, [13, 0, 6, 9]))
+    finally:
+        oracle_mod.set_threads(before)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_infidelity(oracle_mod):
     a = random_state(6, 1)
     assert abs(oracle_mod.infidelity(a, a * np.exp(0.3j))) < 1e-14

@@ -102,6 +102,48 @@ def test_oversized_head_request_does_not_starve():
     assert res[0].start <= later[4]
 
 
+def test_small_requests_pass_a_head_waiting_for_a_stream():
+    """A large head request that waits only for a stream does not hold back
+    small circuits behind it (they take no stream and little memory), and
+    they are not counted as bypasses of the head."""
+    big = [W.Request(0, 0.0, 28, 60, "c128", 1), W.Request(1, 0.001, 28, 60, "c128", 2)]
+    small = [W.Request(2, 0.020, 10, 10, "c128", 3), W.Request(3, 0.030, 10, 10, "c64", 4)]
+    be = FakeBackend(budget=1 << 36)
+    res = {r.rid: r for r in S.serve(big + small, be, max_streams=1, max_bypass=0)}
+    assert be.service(big[0]) > 0.04            # the second large request waits for the stream
+    assert res[1].start >= res[0].done - 1e-9
+    for rid in (2, 3):
+        assert res[rid].start - res[rid].arrival < 1e-3, (rid, res[rid].start, res[rid].arrival)
+        assert res[rid].mode == "batch"
+
+
+def test_bypass_count_limits_competing_requests_only():
+    """With max_bypass = 1, one large request may take a stream past a head
+    that waits for memory; the next large one waits behind the head."""
+    head = W.Request(0, 0.001, 27, 10, "c128", 1)
+    first = W.Request(9, 0.0, 26, 60, "c128", 9)       # holds memory while the head arrives
+    later = [W.Request(i, 0.002 + 0.0001 * i, 20, 10, "c128", 10 + i) for i in range(1, 4)]
+    budget = S.reserve_bytes(27, "c128") + S.reserve_bytes(20, "c128") + S.reserve_bytes(26, "c128") // 2
+    be = FakeBackend(budget=budget)
+    res = {r.rid: r for r in S.serve([first, head] + later, be, max_bypass=1)}
+    passed = [rid for rid in (1, 2, 3) if res[rid].start < res[0].start]
+    assert len(passed) == 1, (passed, {k: (v.start, v.done) for k, v in res.items()})
+
+
+def test_admission_counts_context_buffers():
+    """A context that holds buffers beside its state is charged for them."""
+    class Held(FakeBackend):
+        def held_bytes(self, req):
+            return 1 << 30
+    reqs = [W.Request(i, 0.0, 26, 10, "c128", i) for i in range(4)]
+    budget = 2 * S.state_bytes(26, "c128") + (1 << 30)   # two reserves fit, not two contexts
+    be = Held(budget=budget)
+    res = S.serve(reqs, be)
+    starts = sorted(r.start for r in res)
+    # the second request cannot be admitted beside the first: 2 states + 2 GiB of buffers exceed the budget
+    assert starts[1] > starts[0]
+
+
 def test_served_beats_sequential_plain_on_fake_costs():
     reqs = stream(n_req=60, rate=2.0, n_min=12, n_max=24)
     served = S.summarize(S.serve(reqs, FakeBackend(budget=1 << 36)))

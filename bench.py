@@ -12,7 +12,11 @@ state (16 GiB) stays resident in HBM.  Prints one JSON line:
 * roofline: the dominant kernel's achieved rate against the MI355X peak that
   bounds it, from HIP events around its launches inside the timed steps;
 * cpu_baseline: the CPU oracle (one gate per full pass, complex128) timed on a
-  bounded prefix of the same circuit at the same size on the host cores.
+  bounded prefix of the same circuit at the same size on the host cores;
+* precision: complex64 (and the forced 5-qubit fused-GEMM form on FP32 MFMA)
+  against the complex128 GPU path at 28 and 32 qubits, time and infidelity;
+* serving: a shortened Poisson request stream through the continuous-batching
+  server and through sequential plain solves, p50/p99 latency and gate-apps/s.
 """
 import argparse
 import json
@@ -138,22 +142,129 @@ def copy_reference(gib=16, reps=3):
     return round(best, 1)
 
 
-def cpu_baseline(name, n_prefix):
-    """Oracle on the first n_prefix gates of the same circuit at full size."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, n_prefix=100, n_one_thread=4):
+    """The oracle (plain one-gate-per-pass complex128 simulator, OpenMP over
+    the host cores) on a bounded prefix of the same circuit at full size.
+    Only the gate loop is timed: the |0...0> state is allocated and set
+    before the clock starts.  A second figure runs the next few gates on one
+    thread."""
     import numpy as np
     from oracle import oracle
     from paper_2604_12256_amd import workloads as W
     oracle.build(force=False)
     n, gates = W.config_circuit(name)
+    state = np.zeros(1 << n, dtype=np.complex128)
+    state[0] = 1.0
     sample = gates[:n_prefix]
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
-    state = oracle.run(n, sample)
+    oracle.apply_inplace(n, sample, state)
     dt = time.perf_counter() - t0
+    one = gates[n_prefix:n_prefix + n_one_thread]
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.apply_inplace(n, one, state)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
     del state
-    return {"value": round(len(sample) / dt, 4), "unit": "gate-apps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {len(sample)} gates of {name} ({n} qubits, full 2^{n} complex128 state, "
-                      f"incl. |0> init), {dt:.1f} s"}
+    return {"value": round(len(sample) / dt, 4), "unit": "gate-apps/s", "cores": threads, "kind": "oracle",
+            "sample": f"gates 1..{len(sample)} of {name} ({n} qubits, full 2^{n} complex128 state, one pass per "
+                      f"gate), gate loop only ({dt:.1f} s); |0...0> set up outside the timed region",
+            "cpu": cpu_model(),
+            "one_thread": {"value": round(len(one) / dt1, 4), "unit": "gate-apps/s", "cores": 1,
+                           "sample": f"gates {n_prefix + 1}..{n_prefix + len(one)} of {name}, one thread "
+                                     f"({dt1:.1f} s)"}}
+
+
+def precision_leg():
+    """The precision form: complex64 storage (FP32 arithmetic; 5-qubit fused
+    gates as batched 32x32 complex GEMMs on FP32 MFMA in the forced-fusion
+    form) against the complex128 GPU path, on the 28- and 32-qubit layered
+    circuits.  Infidelity 1 - |<a|b>|^2 / (<a|a><b|b>) in FP64 on the device;
+    times are validate + plan + run (second of two runs)."""
+    import torch
+    from paper_2604_12256_amd import qsim
+    from paper_2604_12256_amd import workloads as W
+
+    def timed(sim, circ):
+        sim.load(circ)
+        sim.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.load(circ)
+        sim.run()
+        return (time.perf_counter() - t0) * 1e3
+
+    rows = []
+    for name in ("layered28", "layered32"):
+        n, gates = W.config_circuit(name)
+        circ = qsim.Circuit(gates)
+        log(f"[bench] precision {name}")
+        ref = qsim.Simulator(n, dtype="c128", opt=qsim.OPT_ALL)
+        t_ref = timed(ref, circ)
+        row = {"workload": f"{name}: {n}-qubit random layered circuit, {len(gates)} gates",
+               "c128_all_passes_ms": round(t_ref, 2)}
+        for key, kw in (("c64_all_passes", dict(opt=qsim.OPT_ALL)),
+                        ("c64_fused_k5_fp32_mfma", dict(opt=qsim.OPT_FUSE, force_fuse_k=5))):
+            low = qsim.Simulator(n, dtype="c64", **kw)
+            t = timed(low, circ)
+            ip = ref.inner(low)
+            inf = 1.0 - abs(ip) ** 2 / (ref.norm() * low.norm())
+            row[key] = {"ms": round(t, 2), "infidelity": float(f"{inf:.3e}"),
+                        "full_passes": low.stats()["full_passes"]}
+            low.close()
+            del low
+            torch.cuda.empty_cache()
+        if name == "layered28":
+            plain = qsim.Simulator(n, dtype="c128", opt=0, state=ref.state)
+            plain.load(circ)
+            t0 = time.perf_counter()
+            plain.run()
+            row["c128_plain_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            plain.close()
+        ref.close()
+        del ref
+        torch.cuda.empty_cache()
+        rows.append(row)
+    return rows
+
+
+def serving_leg(n_requests=40, rate=0.8, seed=5):
+    """A shortened serving stream: Poisson arrivals of random layered
+    circuits (10..30 qubits, 10..60 layers, half complex128 and half
+    complex64), through the continuous-batching server and through
+    sequential plain (gate-by-gate, one request at a time) on the same GPU."""
+    from paper_2604_12256_amd import qsim
+    from paper_2604_12256_amd import serve as S
+    from paper_2604_12256_amd import workloads as W
+    reqs = W.serving_stream(n_requests, rate, seed, 10, 30)
+
+    def progress(tag):
+        def f(done, total):
+            if done % 10 == 0 or done == total:
+                log(f"[bench] serving {tag}: {done}/{total}")
+        return f
+    served = S.summarize(S.serve(reqs, S.GpuBackend(qsim.OPT_ALL, n_streams=4), max_streams=4,
+                                 progress=progress("served")))
+    plain = S.summarize(S.serve_sequential_plain(reqs, S.GpuBackend(0), progress=progress("plain")))
+    keep = ("p50_latency_s", "p99_latency_s", "mean_latency_s", "makespan_s", "gate_apps_per_s", "batched")
+    return {"stream": f"{n_requests} requests, Poisson rate {rate}/s, seed {seed}, 10..30 qubits, 10..60 layers, "
+                      f"half complex128",
+            "served": {k: round(served[k], 4) if isinstance(served[k], float) else served[k] for k in keep},
+            "sequential_plain": {k: round(plain[k], 4) if isinstance(plain[k], float) else plain[k] for k in keep}}
 
 
 def kernel_table(n=30):
@@ -330,7 +441,9 @@ def main():
     ap.add_argument("--workload", default="layered30")
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-prefix", type=int, default=60)
+    ap.add_argument("--cpu-prefix", type=int, default=100)
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--kernels", action="store_true",
                     help="print a per-kernel time / HBM-rate table at 30 qubits instead of the benchmark line")
@@ -388,6 +501,10 @@ def main():
                             "full_passes": d["stats"]["full_passes"],
                             "roofline": roofline(d["per_kind"], "c128", 3, "diag30")}
         out["paper_benchmarks"] = paper_benchmarks()
+    if not args.no_precision:
+        out["precision"] = precision_leg()
+    if not args.no_serving:
+        out["serving"] = serving_leg()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_prefix)

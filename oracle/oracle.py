@@ -124,6 +124,15 @@ def apply(n: int, gates: Sequence, state: np.ndarray) -> np.ndarray:
     return out
 
 
+def apply_inplace(n: int, gates: Sequence, state: np.ndarray) -> None:
+    """Apply the circuit to ``state`` itself (complex128, C-contiguous, 2^n)."""
+    if state.dtype != np.complex128 or state.shape != (1 << n,) or not state.flags.c_contiguous:
+        raise ValueError("oracle: state must be a contiguous complex128 array of 2^n entries")
+    m = _Marshalled(gates)
+    if _load().og_apply(n, m.arr, m.n, state.ctypes.data) != 0:
+        raise ValueError("oracle: invalid circuit")
+
+
 def norm(state: np.ndarray) -> float:
     """sum |a_i|^2 by pairwise summation."""
     state = np.ascontiguousarray(state, dtype=np.complex128)

@@ -319,8 +319,9 @@ def test_diagonal_closed_form_30q():
 
 
 def test_complex64_32q_against_complex128():
-    """Precision form: 32-qubit layered circuit in complex64 (FP32 MFMA
-    fused gates) against the complex128 path on the same GPU."""
+    """32-qubit layered circuit in complex64 on the optimised path (stages,
+    all passes) against the complex128 path on the same GPU.  The forced
+    5-qubit fused-GEMM form is in test_gpu_precision.py."""
     n, gates = W.config_circuit("layered32")
     say("layered32 c64 vs c128")
     a = qsim.Simulator(n, dtype="c128", opt=qsim.OPT_ALL)

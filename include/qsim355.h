@@ -157,6 +157,20 @@ sim_status sim_amplitudes(sim_ctx *ctx, const uint64_t *idx, uint64_t n, double 
  * norm in out[0].  nq <= 16.  out holds 2^nq doubles (host). */
 sim_status sim_probabilities(sim_ctx *ctx, const uint32_t *qubits, uint32_t nq, double *out);
 
+/* sim_probabilities for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: under HIP graph capture, in tight serving
+ * loops, in harnesses that forbid it).  Same arguments, validation, kernels
+ * and results (bitwise) as sim_probabilities, but every intermediate lives in
+ * a static device array of 24 MiB per GPU (held until the process ends)
+ * instead of context-owned buffers: the call allocates nothing.  A request
+ * whose partial sums would exceed that array fails with SIM_E_UNSUPPORTED
+ * (not reachable for nq <= 16 at any supported N).  All contexts on one GPU
+ * share the array, so calls that overlap on one GPU (from several threads or
+ * streams) race; calls in sequence are safe (every value is written before
+ * it is read).  The device is that of the context's creation; out is host
+ * memory of 2^nq doubles; the call synchronises the context's stream. */
+sim_status sim_probabilities_noalloc(sim_ctx *ctx, const uint32_t *qubits, uint32_t nq, double *out);
+
 /* <a|b> = sum_i conj(a_i) b_i between the states of two contexts with the
  * same N (any dtypes), accumulated in FP64 in a fixed order. out[0..1] =
  * (re, im).  Both contexts must have run; launched on a's stream. */

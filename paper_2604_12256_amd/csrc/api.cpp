@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -58,6 +59,43 @@ hipError_t grow(DevBuf &b, size_t bytes)
 
 const char *kNullCtx = "null context";
 
+}  // namespace
+
+// ---- allocation-free outputs ------------------------------------------------
+// Device scratch for callers that cannot allocate (sim_probabilities_noalloc):
+// one array per GPU the library runs on, held until the process ends.  Host
+// code never uses this name as an address (it is a host-side stand-in): the
+// device address comes from hipGetSymbolAddress, once per device, at
+// sim_create.
+namespace {
+constexpr size_t kNoAllocScratchBytes = 24ull << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 }  // namespace
 
 struct sim_plan {
@@ -593,7 +631,9 @@ sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opt
     c->state_bytes = opts->dev_state_bytes;
     c->stream = (hipStream_t)opts->stream;
     if (hipGetDevice(&c->device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
-        hipEventCreate(&c->ev1) != hipSuccess) {
+        hipEventCreate(&c->ev1) != hipSuccess || noalloc_scratch_setup(c->device) != hipSuccess) {
+        if (c->ev0) hipEventDestroy(c->ev0);
+        if (c->ev1) hipEventDestroy(c->ev1);
         delete c;
         return SIM_E_DEVICE;
     }
@@ -754,6 +794,47 @@ sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, do
         for (uint32_t t = 0; t < nq; ++t) b |= ((y >> t) & 1ull) << where[t];
         out[y] = bins[b];
     }
+    return SIM_OK;
+}
+
+sim_status sim_probabilities_noalloc(sim_ctx *c, const uint32_t *qubits, uint32_t nq, double *out)
+{
+    if (!c) return SIM_E_INVAL;
+    if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
+    if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
+    if (nq > 16 || (int)nq > c->n) return fail(c, SIM_E_INVAL, "at most 16 qubits");
+    if (nq && !qubits) return fail(c, SIM_E_INVAL, "qubits is NULL");
+    int ph[16], sorted[16], where[16];
+    for (uint32_t t = 0; t < nq; ++t) {
+        if ((int)qubits[t] >= c->n) return fail(c, SIM_E_INVAL, "qubit out of range");
+        for (uint32_t u = 0; u < t; ++u)
+            if (qubits[u] == qubits[t]) return fail(c, SIM_E_INVAL, "duplicate qubit");
+        ph[t] = c->layout[qubits[t]];
+        sorted[t] = ph[t];
+    }
+    std::sort(sorted, sorted + nq);
+    for (uint32_t t = 0; t < nq; ++t) where[t] = (int)(std::find(sorted, sorted + nq, ph[t]) - sorted);
+    char *base = (char *)noalloc_scratch(c->device);
+    if (!base) return fail(c, SIM_E_STATE, "no scratch on this device (context created elsewhere?)");
+    // scratch layout: per-segment partial bins | bins (ascending physical
+    // order) | bins in the caller's qubit order
+    const size_t nbins = 1ull << nq;
+    const size_t part = qs::marginal_scratch_bytes(c->n, sorted, (int)nq);
+    const size_t off_bins = (part + 255) / 256 * 256;
+    const size_t off_out = off_bins + (nbins * 8 + 255) / 256 * 256;
+    const size_t need = off_out + nbins * 8;
+    if (need > kNoAllocScratchBytes)
+        return fail(c, SIM_E_UNSUPPORTED, "marginal needs " + std::to_string(need) +
+                                              " bytes of scratch, above the static maximum of " +
+                                              std::to_string(kNoAllocScratchBytes));
+    double *bins = (double *)(base + off_bins), *dout = (double *)(base + off_out);
+    hipError_t e = c->dtype == SIM_C128
+                       ? qs::launch_marginal<double>(c->state, c->n, sorted, (int)nq, bins, (double *)base, c->stream)
+                       : qs::launch_marginal<float>(c->state, c->n, sorted, (int)nq, bins, (double *)base, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "marginal");
+    HIPCHK(c, qs::launch_permute_bins(bins, dout, (int)nq, where, c->stream), "bin order");
+    HIPCHK(c, hipMemcpyAsync(out, dout, nbins * 8, hipMemcpyDeviceToHost, c->stream), "copy out");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
     return SIM_OK;
 }
 

@@ -116,6 +116,8 @@ template <typename R> hipError_t launch_gather(const void *state, const uint64_t
 template <typename R> hipError_t launch_marginal(const void *state, int n, const int *q, int nq, double *out,
                                                  double *scratch, hipStream_t s);
 size_t marginal_scratch_bytes(int n, const int *q, int nq);  // q ascending, as passed to launch_marginal
+// out[y] = in[b(y)], bit t of y at bit where[t] of b (device arrays of 2^nq doubles)
+hipError_t launch_permute_bins(const double *in, double *out, int nq, const int *where, hipStream_t s);
 template <typename RA, typename RB> hipError_t launch_inner(const void *a, const void *b, int n, double *out,
                                                             double *scratch, hipStream_t s);
 size_t inner_scratch_bytes(int n);

@@ -621,6 +621,36 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
     return hipGetLastError();
 }
 
+// out[y] = in[b(y)] with bit t of y moved to bit where[t] of b: marginal bins
+// from ascending physical order into the caller's qubit order.
+struct BinPerm {
+    int32_t where[24];
+    int32_t nq, pad;
+};
+
+__global__ __launch_bounds__(kBlock) void k_permute_bins(const double *__restrict__ in, double *__restrict__ out,
+                                                         BinPerm P)
+{
+    const uint64_t y = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (y >= (1ull << P.nq)) return;
+    uint64_t b = 0;
+    for (int t = 0; t < P.nq; ++t) b |= ((y >> t) & 1ull) << P.where[t];
+    out[y] = in[b];
+}
+
+hipError_t launch_permute_bins(const double *in, double *out, int nq, const int *where, hipStream_t s)
+{
+    if (nq < 0 || nq > 24) return hipErrorInvalidValue;
+    BinPerm P{};
+    P.nq = nq;
+    for (int t = 0; t < nq; ++t) {
+        if (where[t] < 0 || where[t] >= nq) return hipErrorInvalidValue;
+        P.where[t] = where[t];
+    }
+    k_permute_bins<<<blocks_for(1ull << nq, kBlock), kBlock, 0, s>>>(in, out, P);
+    return hipGetLastError();
+}
+
 size_t inner_scratch_bytes(int n)
 {
     (void)n;

@@ -102,6 +102,7 @@ def load_library() -> ctypes.CDLL:
         "sim_op_timings": (I, [P, ctypes.POINTER(SimOpTiming), U64, ctypes.POINTER(U64)]),
         "sim_last_error": (ctypes.c_char_p, [P]),
         "sim_device_bytes": (I, [P, ctypes.POINTER(U64)]),
+        "sim_probabilities_noalloc": (I, [P, P, U32, P]),
         "sim_destroy": (I, [P]),
         "sim_run_batch": (I, [P, U32, P]),
         "sim_plan_build": (I, [U32, I, ctypes.POINTER(SimOptions), ctypes.POINTER(SimGate), U64,
@@ -230,6 +231,15 @@ class Simulator:
         out = np.empty(1 << len(q), dtype=np.float64)
         self._check(self._lib.sim_probabilities(self._ctx, q.ctypes.data if len(q) else None, len(q),
                                                 out.ctypes.data))
+        return out
+
+    def probabilities_noalloc(self, qubits: Sequence[int]) -> np.ndarray:
+        """As probabilities(), through the entry point that allocates no
+        device memory (a static per-GPU scratch array)."""
+        q = np.ascontiguousarray(np.asarray(list(qubits), dtype=np.uint32))
+        out = np.empty(1 << len(q), dtype=np.float64)
+        self._check(self._lib.sim_probabilities_noalloc(self._ctx, q.ctypes.data if len(q) else None, len(q),
+                                                        out.ctypes.data))
         return out
 
     def norm(self) -> float:

@@ -254,8 +254,7 @@ def serving_leg(n_requests=40, rate=0.8, seed=5):
 
     def progress(tag):
         def f(done, total):
-            if done % 10 == 0 or done == total:
-                log(f"[bench] serving {tag}: {done}/{total}")
+            log(f"[bench] serving {tag}: {done}/{total}")
         return f
     served = S.summarize(S.serve(reqs, S.GpuBackend(qsim.OPT_ALL, n_streams=4), max_streams=4,
                                  progress=progress("served")))

@@ -99,6 +99,23 @@ typedef struct {
     void *dev_state;           /* device buffer, >= 2^N * 16 B (C128) or 8 B (C64) */
     uint64_t dev_state_bytes;
     void *stream;              /* hipStream_t the context launches on (NULL = default) */
+    /* Host-memory offload (states larger than the device memory given to the
+     * library; the related-work direction of Sec. 2.5 with the cache-blocked
+     * stages of Alg. 2 run window by window).  NULL: the state lives in
+     * dev_state.  Otherwise host_state holds the 2^N amplitudes (pinned host
+     * memory from hipHostMalloc, caller-owned, >= 2^N * 16 B or 8 B), and
+     * dev_state is only a work area of two windows: the largest W with
+     * 2 * 2^W amplitudes <= dev_state_bytes (W <= N - 1) sets the window.
+     * Each offload pass fixes S = N - W outer qubits (a contiguous range of
+     * bit positions that the pass's gates only read as controls or diagonal
+     * indices), copies the 2^S windows through the device in turn, runs the
+     * pass's stages on each and copies it back, with the copies overlapping
+     * the compute on two extra streams.  Needs SIM_OPT_STAGES; the booster
+     * and qubit reordering are not used in this mode.  Outputs:
+     * sim_amplitudes, sim_probabilities and sim_stats; the other output and
+     * measurement calls return SIM_E_UNSUPPORTED. */
+    void *host_state;
+    uint64_t host_state_bytes;
 } sim_options;
 
 typedef struct {
@@ -118,6 +135,10 @@ typedef struct {
     double algorithmic_bytes;  /* bytes the plan moves over the full state */
     double flops;              /* floating-point operations of the plan (estimate) */
     double est_ms;             /* device time of the plan predicted by the optimiser's cost model */
+    uint64_t offload_passes;   /* host-memory offload: passes that stream the whole state through
+                                  the device (0 when the state is device-resident) */
+    uint64_t window_qubits;    /* host-memory offload: qubits W of a device window */
+    double pcie_bytes;         /* host-memory offload: bytes copied between host and device per run */
 } sim_run_stats;
 
 /* Create a context for an n_qubits state of the given dtype (the N-qubit
@@ -264,7 +285,12 @@ typedef enum {
     SIM_OP_DENSE = 2,    /* full-pass dense gate on `qubits` (matrix in payload) */
     SIM_OP_DIAG = 3,     /* full-pass diagonal on `qubits` (table in payload) */
     SIM_OP_STAGE = 4,    /* cache-blocked stage: gates applied chunk by chunk */
-    SIM_OP_PERM = 5      /* qubit permutation: physical bit p -> perm[p] */
+    SIM_OP_PERM = 5,     /* qubit permutation: physical bit p -> perm[p] */
+    SIM_OP_WINDOW = 6    /* host-memory offload pass: the next `nq` ops run on every window
+                            of 2^W amplitudes whose outer qubits (bit positions
+                            qubits[0] .. qubits[0] + qubits[1] - 1) are fixed; the ops' qubits
+                            are physical bits of the full state; qubits[2] = 1 when the
+                            windows start as |0...0> instead of being read */
 } sim_op_kind;
 
 typedef struct {

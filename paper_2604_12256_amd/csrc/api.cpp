@@ -31,6 +31,8 @@ struct Prepared {
     size_t prog_off = 0;        // STAGE: word offset of its program
     int C = 0, nph = 0;
     uint64_t nchunks = 0;
+    int outer_lo = 0, outer_n = 0, pass_ops = 0;  // WINDOW (host-memory offload pass)
+    bool init_window = false;
     bool small = false;         // STAGE run by the small-state kernel
     bool mfma = false;          // DENSE on the matrix cores (table holds the real-ified matrix)
     uint32_t item = 0;          // index of its SmallItem
@@ -127,6 +129,15 @@ struct sim_ctx {
     size_t small_whole_item = 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // host-memory offload: the state lives in `host`; `state` holds two
+    // device windows of 2^window amplitudes; copies run on h2d / d2h
+    void *host = nullptr;
+    void *host_dev = nullptr;              // the same memory as the device addresses it
+    uint64_t host_bytes = 0;
+    int window = 0;
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
+    hipEvent_t ev_pass = nullptr;
     bool timing_pending = false;
     bool profiling = false, profiled = false;
     std::vector<hipEvent_t> op_ev;       // 2 per plan op when profiling
@@ -296,6 +307,47 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
             // selector source bytes: a lane bit of the thread id (0x80 | bit), or
             // the physical position of a chunk or wave bit (wave-uniform)
             bool uni = true;
+            for (int q : sel)
+                if (local_of[q] >= 0 && tid_bit_of_local[local_of[q]] >= 0 && tid_bit_of_local[local_of[q]] < 6)
+                    uni = false;
+            if (uni && sel.size() > 1) {
+                // wave-uniform selectors in ascending physical order (the
+                // table's blocks permuted to match), so that selectors on
+                // consecutive bits are read as one bit field
+                std::vector<int> order(sel.size());
+                for (size_t t = 0; t < sel.size(); ++t) order[t] = (int)t;
+                std::sort(order.begin(), order.end(), [&](int x, int y) { return sel[x] < sel[y]; });
+                std::vector<int> rank(sel.size());
+                for (size_t t = 0; t < sel.size(); ++t) rank[order[t]] = (int)t;
+                const int kmb = __builtin_popcount(mask);
+                const size_t blk = k.type == qs::KOp::DENSE ? (1ull << (2 * kmb)) : (1ull << kmb);
+                const size_t nblk = 1ull << sel.size();
+                std::vector<cplx> perm(blk * nblk);
+                for (size_t bi = 0; bi < nblk; ++bi) {
+                    size_t bo = 0;
+                    for (size_t t = 0; t < sel.size(); ++t) bo |= ((bi >> t) & 1ull) << rank[t];
+                    std::copy(tables.begin() + toff + bi * blk, tables.begin() + toff + (bi + 1) * blk,
+                              perm.begin() + bo * blk);
+                }
+                std::copy(perm.begin(), perm.end(), tables.begin() + toff);
+                std::vector<int> sorted(sel.size());
+                for (size_t t = 0; t < sel.size(); ++t) sorted[rank[t]] = sel[t];
+                sel.swap(sorted);
+            }
+            if (uni && !sel.empty()) {
+                // bit fields: runs of consecutive physical positions (at most
+                // five; more and the kernel reads the source bytes one by one)
+                std::vector<std::pair<int, int>> runs;
+                for (int q : sel) {
+                    if (!runs.empty() && runs.back().first + runs.back().second == q) ++runs.back().second;
+                    else runs.push_back({q, 1});
+                }
+                if (runs.size() <= 5) {
+                    op[10] = (uint32_t)runs.size();
+                    for (size_t r = 0; r < runs.size(); ++r)
+                        op[11 + r] = (uint32_t)runs[r].first | ((uint32_t)runs[r].second << 16);
+                }
+            }
             for (size_t t = 0; t < sel.size(); ++t) {
                 const int q = sel[t];
                 uint32_t code = (uint32_t)q;
@@ -400,6 +452,12 @@ sim_status prepare(sim_ctx *c)
             p.gd = desc_of(op.op, toff);
             break;
         }
+        case SIM_OP_WINDOW:
+            p.outer_lo = op.outer_lo;
+            p.outer_n = op.outer_n;
+            p.pass_ops = op.pass_ops;
+            p.init_window = op.init_window;
+            break;
         case SIM_OP_PERM: {
             // a product of exchanges of low bits (< 6) with high bits
             const int low = std::min(6, op.buffer_qubits);
@@ -420,7 +478,7 @@ sim_status prepare(sim_ctx *c)
         }
         case SIM_OP_STAGE: {
             const bool whole = (int)op.local.size() == op.buffer_qubits;
-            if (whole && op.buffer_qubits <= small_max && op.phases.empty()) {
+            if (whole && op.buffer_qubits <= small_max && op.phases.empty() && !c->window) {
                 p.small = true;
                 qs::SmallItem it{};
                 it.n = (uint32_t)op.buffer_qubits;
@@ -450,7 +508,7 @@ sim_status prepare(sim_ctx *c)
     }
     // the whole circuit as one small-state item, for batched launches of
     // many small circuits (sim_run_batch)
-    c->small_whole = c->n <= small_max;
+    c->small_whole = c->n <= small_max && !c->window;
     if (c->small_whole) {
         qs::SmallItem it{};
         it.n = (uint32_t)c->n;
@@ -520,9 +578,96 @@ sim_status prepare(sim_ctx *c)
     return SIM_OK;
 }
 
+// One op of a host-memory offload pass on a device window (qubits are window
+// bits; xbits carries the window's outer qubits at bits W and above for the
+// stage kernel's selectors).
+template <typename R>
+hipError_t launch_window_op(sim_ctx *c, const Prepared &p, void *buf, uint64_t xbits)
+{
+    const size_t amp = c->amp_bytes();
+    switch (p.kind) {
+    case SIM_OP_STAGE: {
+        qs::StageLaunch L;
+        L.state = buf;
+        L.prog = (const uint32_t *)c->prog.p + p.prog_off;
+        L.tables = c->tables.p;
+        L.n = p.nb;
+        L.C = p.C;
+        L.nphases = p.nph;
+        L.nchunks = p.nchunks;
+        L.xbits = xbits;
+        return qs::launch_stage<R>(L, c->stream);
+    }
+    case SIM_OP_DENSE:
+        if (p.mfma)
+            return qs::launch_dense_mfma<R>(buf, p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp, c->stream);
+        return qs::launch_dense<R>(buf, p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp, c->stream);
+    case SIM_OP_DIAG:
+        return qs::launch_diag_q<R>(buf, p.nb, (int)p.gd.k, p.gd.q, (const char *)c->tables.p + p.gd.table * amp,
+                                    c->stream);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+// Host-memory offload: every pass streams the 2^S windows of the state
+// (outer qubits fixed, rows of 2^lo amplitudes with a stride of 2^(lo+S))
+// through two device buffers: window v is read on the h2d stream while
+// window v - 1 is computed and window v - 2 written back on the d2h stream.
+template <typename R>
+sim_status execute_offload(sim_ctx *c)
+{
+    const size_t amp = c->amp_bytes();
+    const int N = c->n, W = c->window;
+    char *win[2] = {(char *)c->state, (char *)c->state + (amp << W)};
+    bool first_pass = true;
+    for (size_t i = 0; i < c->prep.size();) {
+        const Prepared &w = c->prep[i];
+        if (w.kind != SIM_OP_WINDOW) return fail(c, SIM_E_UNSUPPORTED, "offload plan: op outside a window pass");
+        const int lo = w.outer_lo, S = w.outer_n, m = w.pass_ops;
+        if (S != N - W || lo < 0 || lo + S > N || i + (size_t)m >= c->prep.size())
+            return fail(c, SIM_E_UNSUPPORTED, "offload plan: bad window pass");
+        const uint64_t nwin = 1ull << S;
+        const size_t width = amp << lo;  // row bytes: windows are rows of 2^lo amplitudes
+        // the windows of this pass overlap every window of the previous one:
+        // the first read waits for the last write-back of that pass
+        if (!first_pass) HIPCHK(c, hipStreamWaitEvent(c->h2d, c->ev_pass, 0), "wait");
+        for (uint64_t v = 0; v < nwin; ++v) {
+            const int b = (int)(v & 1);
+            char *dbuf = win[b];
+            if (w.init_window) {
+                HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out[b], 0), "wait");
+                if (v == 0) HIPCHK(c, qs::launch_init<R>(dbuf, W, c->stream), "window init");
+                else HIPCHK(c, hipMemsetAsync(dbuf, 0, amp << W, c->stream), "window init");
+            } else {
+                HIPCHK(c, hipStreamWaitEvent(c->h2d, c->ev_out[b], 0), "wait");
+                HIPCHK(c, qs::launch_window_copy(dbuf, c->host_dev, amp << W, width, S, v, false, c->h2d),
+                       "window read");
+                HIPCHK(c, hipEventRecord(c->ev_in[b], c->h2d), "event record");
+                HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_in[b], 0), "wait");
+            }
+            for (int k = 1; k <= m; ++k) {
+                const hipError_t e = launch_window_op<R>(c, c->prep[i + k], dbuf, v << W);
+                if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+            }
+            HIPCHK(c, hipEventRecord(c->ev_done[b], c->stream), "event record");
+            HIPCHK(c, hipStreamWaitEvent(c->d2h, c->ev_done[b], 0), "wait");
+            HIPCHK(c, qs::launch_window_copy(c->host_dev, dbuf, amp << W, width, S, v, true, c->d2h), "window write");
+            HIPCHK(c, hipEventRecord(c->ev_out[b], c->d2h), "event record");
+        }
+        HIPCHK(c, hipEventRecord(c->ev_pass, c->d2h), "event record");
+        first_pass = false;
+        i += (size_t)m + 1;
+    }
+    // the run ends when the last write-back has landed
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_pass, 0), "wait");
+    return SIM_OK;
+}
+
 template <typename R>
 sim_status execute(sim_ctx *c)
 {
+    if (c->window) return execute_offload<R>(c);
     const size_t amp = c->amp_bytes();
     const R *unused = nullptr;
     (void)unused;
@@ -599,6 +744,53 @@ void fill_stats(const qs::Plan &P, uint64_t n_gates, sim_run_stats *s)
     s->algorithmic_bytes = P.stats.bytes;
     s->flops = P.stats.flops;
     s->est_ms = P.stats.est_ms;
+    s->offload_passes = P.stats.offload_passes;
+    s->window_qubits = (uint64_t)P.opt.window_qubits;
+    s->pcie_bytes = P.stats.pcie_bytes;
+}
+
+// Marginal of an offloaded state: its top-qubit slices of 2^W amplitudes
+// pass through the device one after the other; each slice's marginal over
+// the selected qubits below W goes to the host and is added, slice by slice
+// in order, into the bins its top bits select (deterministic).
+sim_status offload_marginal(sim_ctx *c, const std::vector<int> &ph, double *out)
+{
+    const int N = c->n, W = c->window, nq = (int)ph.size();
+    const size_t amp = c->amp_bytes();
+    std::vector<int> inner;
+    for (int q : ph)
+        if (q < W) inner.push_back(q);
+    std::sort(inner.begin(), inner.end());
+    const int ki = (int)inner.size();
+    const size_t nib = 1ull << ki;
+    const size_t scr = qs::marginal_scratch_bytes(W, inner.data(), ki);
+    HIPCHK(c, grow(c->scratch, scr + nib * 8 + 64), "scratch allocation");
+    double *dbins = (double *)((char *)c->scratch.p + ((scr + 63) / 64) * 64);
+    std::vector<double> bins(nib);
+    std::fill(out, out + (1ull << nq), 0.0);
+    for (uint64_t v = 0; v < (1ull << (N - W)); ++v) {
+        HIPCHK(c, hipMemcpyAsync(c->state, (const char *)c->host + (v * amp << W), amp << W, hipMemcpyHostToDevice,
+                                 c->stream),
+               "slice read");
+        const hipError_t e =
+            c->dtype == SIM_C128
+                ? qs::launch_marginal<double>(c->state, W, inner.data(), ki, dbins, (double *)c->scratch.p, c->stream)
+                : qs::launch_marginal<float>(c->state, W, inner.data(), ki, dbins, (double *)c->scratch.p, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "marginal");
+        HIPCHK(c, hipMemcpyAsync(bins.data(), dbins, nib * 8, hipMemcpyDeviceToHost, c->stream), "copy out");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+        for (size_t yb = 0; yb < nib; ++yb) {
+            size_t y = 0;
+            for (int t = 0; t < nq; ++t) {
+                uint64_t bit;
+                if (ph[t] < W) bit = (yb >> (std::find(inner.begin(), inner.end(), ph[t]) - inner.begin())) & 1;
+                else bit = (v >> (ph[t] - W)) & 1;
+                y |= (size_t)bit << t;
+            }
+            out[y] += bins[yb];
+        }
+    }
+    return SIM_OK;
 }
 
 }  // namespace
@@ -621,7 +813,14 @@ sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opt
     if (dtype != SIM_C128 && dtype != SIM_C64) return SIM_E_INVAL;
     if (!opts->dev_state) return SIM_E_INVAL;
     const uint64_t need = (dtype == SIM_C128 ? 16ull : 8ull) << n_qubits;
-    if (opts->dev_state_bytes < need) return SIM_E_NOMEM;
+    if (opts->host_state) {
+        // host-memory offload: the state is in host memory, the device
+        // buffer holds two windows
+        if (opts->host_state_bytes < need) return SIM_E_NOMEM;
+        if (!(opts->opt & SIM_OPT_STAGES)) return SIM_E_UNSUPPORTED;
+    } else if (opts->dev_state_bytes < need) {
+        return SIM_E_NOMEM;
+    }
     sim_ctx *c = new (std::nothrow) sim_ctx();
     if (!c) return SIM_E_NOMEM;
     c->n = (int)n_qubits;
@@ -630,12 +829,36 @@ sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opt
     c->state = opts->dev_state;
     c->state_bytes = opts->dev_state_bytes;
     c->stream = (hipStream_t)opts->stream;
+    if (opts->host_state) {
+        c->host = opts->host_state;
+        c->host_bytes = opts->host_state_bytes;
+        c->window = c->opt.window_qubits;
+        // a window holds at least one stage chunk
+        if (c->window < std::max<int>((int)c->opt.C, 6 + c->opt.reg_bits)) {
+            delete c;
+            return SIM_E_NOMEM;
+        }
+    }
     if (hipGetDevice(&c->device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess || noalloc_scratch_setup(c->device) != hipSuccess) {
         if (c->ev0) hipEventDestroy(c->ev0);
         if (c->ev1) hipEventDestroy(c->ev1);
         delete c;
         return SIM_E_DEVICE;
+    }
+    if (c->window) {
+        bool ok = hipHostGetDevicePointer(&c->host_dev, c->host, 0) == hipSuccess &&
+                  hipStreamCreateWithFlags(&c->h2d, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&c->d2h, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_pass, hipEventDisableTiming) == hipSuccess;
+        for (int b = 0; b < 2 && ok; ++b)
+            ok = hipEventCreateWithFlags(&c->ev_in[b], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&c->ev_done[b], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&c->ev_out[b], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            sim_destroy(c);
+            return SIM_E_DEVICE;
+        }
     }
     *out = c;
     return SIM_OK;
@@ -681,14 +904,14 @@ sim_status sim_run_async(sim_ctx *c)
 {
     if (!c) return SIM_E_INVAL;
     if (!c->loaded) return fail(c, SIM_E_STATE, "no circuit loaded");
-    if (c->profiling) {
+    if (c->profiling && !c->window) {
         while (c->op_ev.size() < 2 * c->prep.size()) {
             hipEvent_t ev;
             HIPCHK(c, hipEventCreate(&ev), "event create");
             c->op_ev.push_back(ev);
         }
     }
-    c->profiled = c->profiling;
+    c->profiled = c->profiling && !c->window;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream), "event record");
     sim_status s = c->dtype == SIM_C128 ? execute<double>(c) : execute<float>(c);
     if (s != SIM_OK) return s;
@@ -727,6 +950,24 @@ sim_status sim_amplitudes(sim_ctx *c, const uint64_t *idx, uint64_t m, double *o
         return y;
     };
     HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");
+    if (c->window) {
+        // offload: the final state is in host memory (logical = physical order)
+        if (idx)
+            for (uint64_t i = 0; i < m; ++i)
+                if (idx[i] >= len) return fail(c, SIM_E_INVAL, "amplitude index out of range");
+        if (!idx && m != len) return fail(c, SIM_E_INVAL, "idx NULL requires n == 2^N");
+        for (uint64_t i = 0; i < m; ++i) {
+            const uint64_t x = idx ? idx[i] : i;
+            if (c->dtype == SIM_C128) {
+                out[2 * i] = ((const double *)c->host)[2 * x];
+                out[2 * i + 1] = ((const double *)c->host)[2 * x + 1];
+            } else {
+                out[2 * i] = ((const float *)c->host)[2 * x];
+                out[2 * i + 1] = ((const float *)c->host)[2 * x + 1];
+            }
+        }
+        return SIM_OK;
+    }
     const uint64_t kBatch = 1ull << 22;
     if (!idx) {
         if (m != len) return fail(c, SIM_E_INVAL, "idx NULL requires n == 2^N");
@@ -770,6 +1011,7 @@ sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, do
             if (qubits[u] == qubits[t]) return fail(c, SIM_E_INVAL, "duplicate qubit");
         ph[t] = c->layout[qubits[t]];
     }
+    if (c->window) return offload_marginal(c, ph, out);
     std::vector<int> sorted = ph;
     std::sort(sorted.begin(), sorted.end());
     const size_t nbins = 1ull << nq;
@@ -800,6 +1042,7 @@ sim_status sim_probabilities(sim_ctx *c, const uint32_t *qubits, uint32_t nq, do
 sim_status sim_probabilities_noalloc(sim_ctx *c, const uint32_t *qubits, uint32_t nq, double *out)
 {
     if (!c) return SIM_E_INVAL;
+    if (c->window) return fail(c, SIM_E_UNSUPPORTED, "not available for a state in host memory");
     if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
     if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
     if (nq > 16 || (int)nq > c->n) return fail(c, SIM_E_INVAL, "at most 16 qubits");
@@ -843,6 +1086,7 @@ sim_status sim_probabilities_noalloc(sim_ctx *c, const uint32_t *qubits, uint32_
 sim_status sim_measure(sim_ctx *c, uint32_t qubit, double u, uint32_t *outcome, double *prob)
 {
     if (!c) return SIM_E_INVAL;
+    if (c->window) return fail(c, SIM_E_UNSUPPORTED, "not available for a state in host memory");
     if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
     if ((int)qubit >= c->n) return fail(c, SIM_E_INVAL, "qubit out of range");
     if (!(u >= 0.0 && u < 1.0)) return fail(c, SIM_E_INVAL, "u must lie in [0, 1)");
@@ -868,6 +1112,7 @@ sim_status sim_measure(sim_ctx *c, uint32_t qubit, double u, uint32_t *outcome, 
 sim_status sim_sample(sim_ctx *c, const double *u, uint64_t n_shots, uint64_t *out)
 {
     if (!c) return SIM_E_INVAL;
+    if (c->window) return fail(c, SIM_E_UNSUPPORTED, "not available for a state in host memory");
     if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
     if (n_shots == 0) return SIM_OK;
     if (!u || !out) return fail(c, SIM_E_INVAL, "u or out is NULL");
@@ -968,6 +1213,7 @@ sim_status sim_sample(sim_ctx *c, const double *u, uint64_t n_shots, uint64_t *o
 sim_status sim_expect_z(sim_ctx *c, const uint64_t *masks, uint32_t n_masks, double *out)
 {
     if (!c) return SIM_E_INVAL;
+    if (c->window) return fail(c, SIM_E_UNSUPPORTED, "not available for a state in host memory");
     if (!c->ran) return fail(c, SIM_E_STATE, "sim_run has not completed");
     if (n_masks == 0) return SIM_OK;
     if (!masks || !out) return fail(c, SIM_E_INVAL, "masks or out is NULL");
@@ -1015,6 +1261,7 @@ sim_status sim_inner(sim_ctx *a, sim_ctx *b, double *out)
     if (!out) return fail(a, SIM_E_INVAL, "out is NULL");
     if (a->n != b->n) return fail(a, SIM_E_INVAL, "qubit counts differ");
     if (!a->ran || !b->ran) return fail(a, SIM_E_STATE, "both contexts must have run");
+    if (a->window || b->window) return fail(a, SIM_E_UNSUPPORTED, "not available for a state in host memory");
     HIPCHK(a, hipStreamSynchronize(b->stream), "synchronize");
     if (a->layout != b->layout) {
         // element i of a (physical) is logical x = pa^-1(i); b holds it at pb(x)
@@ -1111,6 +1358,14 @@ sim_status sim_destroy(sim_ctx *c)
 {
     if (!c) return SIM_E_INVAL;
     hipStreamSynchronize(c->stream);
+    if (c->h2d) hipStreamSynchronize(c->h2d);
+    if (c->d2h) hipStreamSynchronize(c->d2h);
+    for (int b = 0; b < 2; ++b)
+        for (hipEvent_t ev : {c->ev_in[b], c->ev_done[b], c->ev_out[b]})
+            if (ev) hipEventDestroy(ev);
+    if (c->ev_pass) hipEventDestroy(c->ev_pass);
+    if (c->h2d) hipStreamDestroy(c->h2d);
+    if (c->d2h) hipStreamDestroy(c->d2h);
     for (DevBuf *b : {&c->tables, &c->prog, &c->gdesc, &c->items, &c->scratch, &c->io})
         if (b->p) hipFree(b->p);
     for (DevBuf &b : c->subbufs)
@@ -1185,6 +1440,28 @@ sim_status sim_plan_build(uint32_t n_qubits, sim_dtype dtype, const sim_options 
 
 uint64_t sim_plan_num_ops(const sim_plan *p) { return p ? p->plan.ops.size() : 0; }
 
+namespace {
+// Physical bit of qubit q of op i: ops inside a host-memory offload pass
+// name window bits.
+struct WindowMap {
+    int lo = 0, n = 0, nq = 0;
+    bool on = false;
+    int operator()(int q) const { return on ? qs::window_to_physical(q, lo, n, nq) : q; }
+};
+WindowMap window_map(const qs::Plan &P, uint64_t i)
+{
+    WindowMap m;
+    for (uint64_t j = 0; j < P.ops.size() && j < i; ++j)
+        if (P.ops[j].kind == SIM_OP_WINDOW && j + (uint64_t)P.ops[j].pass_ops >= i) {
+            m.on = true;
+            m.lo = P.ops[j].outer_lo;
+            m.n = P.ops[j].outer_n;
+            m.nq = P.n;
+        }
+    return m;
+}
+}  // namespace
+
 sim_status sim_plan_get_op(const sim_plan *p, uint64_t i, sim_plan_op *op, double *payload)
 {
     if (!p || !op || i >= p->plan.ops.size()) return SIM_E_INVAL;
@@ -1195,9 +1472,16 @@ sim_status sim_plan_get_op(const sim_plan *p, uint64_t i, sim_plan_op *op, doubl
     op->buffer_qubits = (uint32_t)o.buffer_qubits;
     op->src_lo = (uint32_t)o.src_lo;
     op->src_hi = (uint32_t)o.src_hi;
-    if (o.kind == SIM_OP_DENSE || o.kind == SIM_OP_DIAG) {
+    const WindowMap wm = window_map(p->plan, i);
+    if (wm.on) op->buffer_qubits = (uint32_t)p->plan.n;  // reported on the full state
+    if (o.kind == SIM_OP_WINDOW) {
+        op->nq = (uint32_t)o.pass_ops;
+        op->qubits[0] = (uint32_t)o.outer_lo;
+        op->qubits[1] = (uint32_t)o.outer_n;
+        op->qubits[2] = o.init_window ? 1u : 0u;
+    } else if (o.kind == SIM_OP_DENSE || o.kind == SIM_OP_DIAG) {
         op->nq = (uint32_t)o.op.q.size();
-        for (size_t t = 0; t < o.op.q.size() && t < 32; ++t) op->qubits[t] = (uint32_t)o.op.q[t];
+        for (size_t t = 0; t < o.op.q.size() && t < 32; ++t) op->qubits[t] = (uint32_t)wm(o.op.q[t]);
         op->payload_len = o.op.m.size();
         if (payload)
             for (size_t t = 0; t < o.op.m.size(); ++t) {
@@ -1207,7 +1491,7 @@ sim_status sim_plan_get_op(const sim_plan *p, uint64_t i, sim_plan_op *op, doubl
     } else if (o.kind == SIM_OP_STAGE) {
         op->nq = (uint32_t)o.gates.size();
         op->local_qubits = (uint32_t)o.local.size();
-        for (size_t t = 0; t < o.local.size() && t < 32; ++t) op->qubits[t] = (uint32_t)o.local[t];
+        for (size_t t = 0; t < o.local.size() && t < 32; ++t) op->qubits[t] = (uint32_t)wm(o.local[t]);
         op->n_phases = (uint32_t)o.phases.size();
     } else if (o.kind == SIM_OP_PERM) {
         op->nq = (uint32_t)o.perm.size();
@@ -1222,10 +1506,11 @@ sim_status sim_plan_stage_gate(const sim_plan *p, uint64_t op_index, uint64_t i,
     const qs::PlanOp &o = p->plan.ops[op_index];
     if (o.kind != SIM_OP_STAGE || i >= o.gates.size()) return SIM_E_INVAL;
     const qs::Operator &x = o.gates[i];
+    const WindowMap wm = window_map(p->plan, op_index);
     std::memset(g, 0, sizeof(*g));
     g->diagonal = x.diag ? 1 : 0;
     g->nq = (uint32_t)x.q.size();
-    for (size_t t = 0; t < x.q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)x.q[t];
+    for (size_t t = 0; t < x.q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)wm(x.q[t]);
     g->payload_len = x.m.size();
     if (payload)
         for (size_t t = 0; t < x.m.size(); ++t) {
@@ -1241,6 +1526,7 @@ sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64
     if (!p || !g || op_index >= p->plan.ops.size()) return SIM_E_INVAL;
     const qs::PlanOp &o = p->plan.ops[op_index];
     if (o.kind != SIM_OP_STAGE) return SIM_E_INVAL;
+    const WindowMap wm = window_map(p->plan, op_index);
     for (const qs::Phase &ph : o.phases) {
         if (i >= ph.ops.size()) {
             i -= ph.ops.size();
@@ -1254,7 +1540,7 @@ sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64
             for (int q : k.dq)
                 for (int b : ph.reg)
                     if (o.local[b] == q) g->n_register++;
-            for (size_t t = 0; t < k.dq.size() && t < 16; ++t) g->qubits[t] = (uint32_t)k.dq[t];
+            for (size_t t = 0; t < k.dq.size() && t < 16; ++t) g->qubits[t] = (uint32_t)wm(k.dq[t]);
             g->payload_len = k.table.size();
             if (payload)
                 for (size_t t = 0; t < k.table.size(); ++t) {
@@ -1271,7 +1557,7 @@ sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64
         g->diagonal = 0;
         g->nq = (uint32_t)q.size();
         g->n_register = (uint32_t)kr;
-        for (size_t t = 0; t < q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)q[t];
+        for (size_t t = 0; t < q.size() && t < 16; ++t) g->qubits[t] = (uint32_t)wm(q[t]);
         const uint64_t D = 1ull << (kr + ks), dr = 1ull << kr;
         g->payload_len = D * D;
         if (payload) {

@@ -146,10 +146,16 @@ struct StageLaunch {
     const void *tables;      // device table arena
     int n, C, nphases;
     uint64_t nchunks;
+    uint64_t xbits = 0;      // bits OR-ed into the wave-uniform base for selectors only (the
+                             // outer qubits of a host-memory offload window, at bits >= n)
 };
 template <typename R> hipError_t launch_stage(const StageLaunch &L, hipStream_t s);
 
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+// host-memory offload: window v (outer qubits fixed) between the mapped host
+// state and a device window; rows of row_bytes, 2^S windows interleaved
+hipError_t launch_window_copy(void *dst, const void *src, uint64_t window_bytes, uint64_t row_bytes, int S,
+                              uint64_t v, bool to_host, hipStream_t s);
 
 // ---- measurement (kernels_measure.hip) ----
 // Inverse-CDF sampling inside blocks of 2^nlow consecutive logical indices:

@@ -93,6 +93,13 @@ struct PlanOp {
     double flops = 0;                 // floating-point operations of the op
     double bytes = 0;                 // algorithmic HBM bytes of the op
     double est_s = 0;                 // STAGE: modelled device seconds of its operators
+    // WINDOW (host-memory offload pass): the next pass_ops ops run on each
+    // window of the state whose outer qubits [outer_lo, outer_lo + outer_n)
+    // are fixed; their qubits are window bits (physical bit p below outer_lo
+    // stays p, one above the range becomes p - outer_n, and the outer bits
+    // sit at W, W + 1, ... where only selectors may read them)
+    int outer_lo = 0, outer_n = 0, pass_ops = 0;
+    bool init_window = false;         // the windows start as |0...0> instead of being read
 };
 
 struct PlanStats {
@@ -100,12 +107,15 @@ struct PlanStats {
              n_kron = 0, n_perm = 0, n_subruns = 0, n_ops = 0;
     double bytes = 0, flops = 0, plan_ms = 0, est_ms = 0;
     uint64_t dd_visits = 0, booster_gates = 0, booster_groups = 0;
+    uint64_t offload_passes = 0;
+    double pcie_bytes = 0;
 };
 
 struct Options {
     uint32_t opt = 0, C = 0, F = 5, D = 10, B = 4, force_fuse_k = 0;
     int reg_bits = 4;                 // register bits per thread in a stage
     int fixed_low = 6;                // physical bits every stage keeps local (coalescing; set per dtype)
+    int window_qubits = 0;            // host-memory offload: qubits of a device window (0 = off)
 };
 
 struct Plan {
@@ -122,6 +132,26 @@ struct Plan {
 Options resolve_options(const sim_options *o, sim_dtype dtype, int n);
 // Builds the plan (all host passes).  Throws std::runtime_error on failure.
 void build_plan(Plan &plan, const std::vector<Operator> &gates);
+
+// Host-memory offload: physical bit of window bit w of a pass whose outer
+// range is [lo, lo + n) in a state of `nq` qubits (window bits at and above
+// nq - n name the outer bits, in order).
+inline int window_to_physical(int w, int lo, int n, int nq)
+{
+    const int W = nq - n;
+    if (w >= W) return lo + (w - W);
+    return w < lo ? w : w + n;
+}
+inline int physical_to_window(int p, int lo, int n, int nq)
+{
+    const int W = nq - n;
+    if (p < lo) return p;
+    if (p < lo + n) return W + (p - lo);
+    return p - n;
+}
+// Window qubits for a device work area of `dev_bytes` holding two windows
+// (at most nq - 1); 0 if not even one qubit fits.
+int offload_window_qubits(uint64_t dev_bytes, uint64_t amp_bytes, int nq);
 
 // Passes, exposed for the plan builder and its tests.
 std::vector<Operator> diagonal_detector(int n, int D, const std::vector<Operator> &in, uint64_t *visits);

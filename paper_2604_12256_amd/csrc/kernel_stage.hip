@@ -31,6 +31,9 @@
 //           [1,2] table byte offset   [3..9] selector sources (bytes): 0x80 | b is
 //           lane bit b of the thread id, any other value the physical position of
 //           a chunk or wave bit
+//           [10] wave-uniform selectors as bit fields: number of fields (0: read
+//           the source bytes)   [11..15] field r: first physical position |
+//           width << 16 (fields fill the selector from bit 0 up)
 //   A dense op's table holds 2^nsel matrices of (2^k)^2 entries, a diagonal
 //   op's 2^nsel blocks of 2^k factors (k = popcount of the register mask).
 #include "device.hpp"
@@ -307,7 +310,7 @@ template <typename R, int RB>
 __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
                                                             const uint32_t *__restrict__ Pg,
                                                             const c2_t<R> *__restrict__ tables,
-                                                            uint64_t nchunks)
+                                                            uint64_t nchunks, uint64_t xbits)
 {
     using V = c2_t<R>;
     const QS_CONST uint32_t *P = as_const(Pg);
@@ -340,8 +343,13 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     for (int i = 0; i < C - RB; ++i) neutral_t[i / 4] |= (uint32_t)i << (8 * (i % 4));
 
     V amp[NR];
-    for (uint64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-        const uint64_t cbase = deposit(chunk, Gmask);
+    // chunk bits at their physical positions: deposited once, then advanced
+    // by a masked add (the bits outside the mask are set, so that carries run
+    // through them)
+    const uint64_t cstep = deposit(gridDim.x, Gmask);
+    uint64_t cbase = deposit(blockIdx.x, Gmask);
+    for (uint64_t chunk = blockIdx.x; chunk < nchunks;
+         chunk += gridDim.x, cbase = ((cbase | ~Gmask) + cstep) & Gmask) {
         // chunk bits, thread bits and register bits are disjoint: each
         // amplitude is a per-thread pointer plus a wave-uniform offset
         V *const pt = state + (cbase | tphys);
@@ -366,8 +374,9 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
                 cur_off = ph + 16;
             }
             // wave-uniform base: chunk bits and the wave bits of the thread id
-            // at their physical positions
-            uint64_t ub = cbase;
+            // at their physical positions, and any bits beyond the buffer
+            // (outer qubits of an offload window)
+            uint64_t ub = cbase | xbits;
             const uint32_t nwave = ph[3];
             for (uint32_t i = 0; i < nwave; ++i)
                 ub |= (uint64_t)((wave >> i) & 1u) << byte_at(ph + 8, (int)i);
@@ -377,7 +386,21 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
                 const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0xffu, shift = head >> 25;
                 const uint64_t toff = (uint64_t)rec.w[1] | ((uint64_t)rec.w[2] << 32);
                 if ((head >> 24) & 1u) {
-                    const uint32_t sel = gather_sel<false>(rec, recs + 16 * o, nsel, ub, tid);
+                    uint32_t sel;
+                    const uint32_t nfield = rec.w[10];
+                    if (nfield) {
+                        sel = 0;
+                        uint32_t u = 0;
+#pragma unroll
+                        for (uint32_t f = 0; f < 5; ++f)
+                            if (f < nfield) {
+                                const uint32_t d = rec.w[11 + f], w = d >> 16;
+                                sel |= ((uint32_t)(ub >> (d & 63u)) & ((1u << w) - 1u)) << u;
+                                u += w;
+                            }
+                    } else {
+                        sel = gather_sel<false>(rec, recs + 16 * o, nsel, ub, tid);
+                    }
                     const QS_CONST R *m = reinterpret_cast<const QS_CONST R *>(ctables + toff + ((uint64_t)sel << shift));
                     if ((head & 0xffu) == 1u) dispatch_dense<R, RB>(mask, amp, m);
                     else dispatch_diag<R, RB>(mask, amp, m);
@@ -430,7 +453,7 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     uint64_t grid = L.nchunks;
     if (grid > (1ull << 15)) grid = 1ull << 15;
     k_stage<R, RB><<<(uint32_t)grid, threads, lds, s>>>((c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables,
-                                                        L.nchunks);
+                                                        L.nchunks, L.xbits);
     return hipGetLastError();
 }
 

@@ -621,6 +621,35 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
     return hipGetLastError();
 }
 
+// Host-memory offload: copies window v of the state between the host (mapped
+// pinned memory, read or written by the GPU over the host link) and a device
+// window.  In 16-byte units: the window is rows of 2^r units; window unit
+// i = (row << r) | off is state unit ((row << S | v) << r) | off.
+__global__ __launch_bounds__(kBlock) void k_window_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                        uint64_t units, uint32_t r, uint32_t S, uint64_t v,
+                                                        uint32_t to_host)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t omask = (1ull << r) - 1;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < units; i += stride) {
+        const uint64_t h = ((((i >> r) << S) | v) << r) | (i & omask);
+        if (to_host) dst[h] = src[i];
+        else dst[i] = src[h];
+    }
+}
+
+hipError_t launch_window_copy(void *dst, const void *src, uint64_t window_bytes, uint64_t row_bytes, int S,
+                              uint64_t v, bool to_host, hipStream_t s)
+{
+    if (row_bytes < 16 || (row_bytes & (row_bytes - 1)) || window_bytes % row_bytes || S < 0 || S > 40)
+        return hipErrorInvalidValue;
+    const uint64_t units = window_bytes / 16;
+    const uint32_t r = (uint32_t)__builtin_ctzll(row_bytes / 16);
+    k_window_copy<<<blocks_for(units, kBlock * 8), kBlock, 0, s>>>((uint4 *)dst, (const uint4 *)src, units, r,
+                                                                  (uint32_t)S, v, to_host ? 1u : 0u);
+    return hipGetLastError();
+}
+
 // out[y] = in[b(y)] with bit t of y moved to bit where[t] of b: marginal bins
 // from ascending physical order into the caller's qubit order.
 struct BinPerm {

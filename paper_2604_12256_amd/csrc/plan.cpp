@@ -101,8 +101,21 @@ Options resolve_options(const sim_options *o, sim_dtype dtype, int n)
     if (r.D > 20) r.D = 20;
     if (r.D < 1) r.D = 1;
     if (r.B < 1) r.B = 1;
-    (void)n;
+    if (o && o->host_state) {
+        // host-memory offload: windows of the state pass through the device;
+        // the merge booster (sub-states) and qubit reordering (permutation
+        // passes) are not used in this mode
+        r.window_qubits = offload_window_qubits(o->dev_state_bytes, dtype == SIM_C128 ? 16 : 8, n);
+        r.opt &= ~(uint32_t)(SIM_OPT_BOOST | SIM_OPT_REMAP);
+    }
     return r;
+}
+
+int offload_window_qubits(uint64_t dev_bytes, uint64_t amp_bytes, int nq)
+{
+    int W = 0;
+    while (W + 1 <= nq - 1 && (2 * amp_bytes << (W + 1)) <= dev_bytes) ++W;
+    return (2 * amp_bytes << W) <= dev_bytes ? W : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -740,14 +753,14 @@ struct Builder {
     }
 
     void greedy_stage(const Masks &M, const std::vector<int> &rem, int C, int low, int r, uint64_t *Lout,
-                      std::vector<int> *take, std::vector<int> *left) const
+                      std::vector<int> *take, std::vector<int> *left, uint64_t avail = ~0ull) const
     {
         uint64_t L = (1ull << low) - 1;
         uint64_t blocked = 0;
         for (int gi : rem) {
             const uint64_t qs = M.qs[gi];
             const uint64_t nd = M.nd[gi];
-            if ((qs & blocked) || popc(nd) > r) {
+            if ((qs & blocked) || popc(nd) > r || (nd & ~avail)) {
                 blocked |= qs;
                 if (left) left->push_back(gi);
                 continue;
@@ -948,7 +961,13 @@ struct Builder {
         return true;
     }
 
-    void stages(int buffer, int nb, const std::vector<Operator> &gates)
+    // Cache-blocked stages over the buffer.  In window mode (host-memory
+    // offload) the gates may also name bits at and above nb (the outer bits
+    // of the pass, fixed per window): they can only select blocks or index
+    // diagonals, so a gate that needs one locally, or a full-pass gate that
+    // touches one, ends the pass; the gates not taken are returned (indices
+    // into `gates`, in circuit order).
+    std::vector<int> stages(int buffer, int nb, const std::vector<Operator> &gates, bool window = false)
     {
         const int C = std::min<int>((int)o.C, nb), r = o.reg_bits;
         const int low = std::min(o.fixed_low, C);
@@ -967,11 +986,13 @@ struct Builder {
             M.nd[i] = tile_need(pg[i]);
         }
         const double nb_amps = std::ldexp(1.0, nb);
-        const bool remap = buffer == 0 && (o.opt & SIM_OPT_REMAP) && nb > C;
+        const bool remap = buffer == 0 && (o.opt & SIM_OPT_REMAP) && nb > C && !window;
+        const uint64_t avail = nb >= 64 ? ~0ull : ((1ull << nb) - 1);
         while (!rem.empty()) {
             if (remap) maybe_remap(pg, M, rem, nb, C, low, r);
             const Operator &first = pg[rem.front()];
             if (popc(M.nd[rem.front()]) > r) {  // beyond the register tile: one full pass
+                if (M.qs[rem.front()] & ~avail) break;  // on an outer bit: not in this pass
                 add_full_pass_op(buffer, nb, first);
                 account_full_pass(buffer, nb, first);
                 rem.erase(rem.begin());
@@ -979,7 +1000,7 @@ struct Builder {
             }
             uint64_t L;
             std::vector<int> take, left;
-            greedy_stage(M, rem, C, low, r, &L, &take, &left);
+            greedy_stage(M, rem, C, low, r, &L, &take, &left, avail);
             for (int q = 0; q < nb && popc(L) < C; ++q) L |= 1ull << q;
             if (nb > C) {
                 L = refine_local(M, rem, L, low, r, nb);
@@ -987,6 +1008,7 @@ struct Builder {
                 left.clear();
                 frontier(M, rem, L, r, ~0ull, &take, &left);
             }
+            if (take.empty()) break;  // window mode: every frontier gate needs an outer bit
             PlanOp st;
             st.kind = SIM_OP_STAGE;
             st.buffer = buffer;
@@ -1011,6 +1033,105 @@ struct Builder {
                 std::sort(left.begin(), left.end());
             }
             rem.swap(left);
+        }
+        if (!rem.empty() && !window) throw std::runtime_error("stage partition made no progress");
+        return rem;
+    }
+
+    // Host-memory offload (the state lives in host memory; the device holds
+    // two windows of 2^W amplitudes).  A pass fixes S = N - W outer qubits, a
+    // contiguous range of bit positions, so that every window is a 2D block
+    // of the state (rows of 2^lo amplitudes); inside the pass the outer
+    // qubits are constants of the window, read only by selectors and
+    // diagonal tables.  The range is chosen so that the gate frontier runs
+    // furthest before a gate needs one of its qubits locally; the pass's
+    // stages are the cache-blocked stages of the window, and it ends when
+    // every frontier gate needs an outer qubit.  The first pass creates
+    // |0...0> in the windows instead of reading them.
+    void offload(const std::vector<Operator> &in)
+    {
+        const int N = plan.n, W = o.window_qubits, S = N - W;
+        const int lo_min = std::min(7, W);
+        std::vector<Operator> gates = in;
+        if (o.opt & SIM_OPT_DIAG) {
+            uint64_t v = 0;
+            gates = diagonal_detector(N, (int)o.D, gates, &v);
+            plan.stats.dd_visits += v;
+        }
+        std::vector<uint64_t> qs(gates.size()), nd(gates.size());
+        for (size_t i = 0; i < gates.size(); ++i) {
+            qs[i] = gates[i].mask();
+            nd[i] = tile_need(gates[i]);
+        }
+        std::vector<int> rem(gates.size());
+        for (size_t i = 0; i < gates.size(); ++i) rem[i] = (int)i;
+        const double amp = amp_bytes(), scale = std::ldexp(1.0, S);
+        const uint64_t all = (N >= 64) ? ~0ull : ((1ull << N) - 1);
+        bool first = true;
+        while (first || !rem.empty()) {
+            // outer range: the frontier takes the most gates before it stops;
+            // ranges at bit 7 or above first (rows of at least 128
+            // amplitudes), then any range above the always-local low bits
+            int best_lo = N - S;
+            size_t best = 0;
+            for (const int floor_lo : {lo_min, std::min(lo_min, o.fixed_low)}) {
+                for (int lo = N - S; lo >= floor_lo; --lo) {
+                    const uint64_t R = ((1ull << S) - 1) << lo;
+                    uint64_t blocked = 0;
+                    size_t n = 0;
+                    for (size_t i = 0; i < rem.size() && i < 4000; ++i) {
+                        const int g = rem[i];
+                        if ((qs[g] & blocked) || (nd[g] & R) || (popc(nd[g]) > o.reg_bits && (qs[g] & R))) {
+                            blocked |= qs[g];
+                            if ((blocked & all) == all) break;
+                            continue;
+                        }
+                        ++n;
+                    }
+                    if (n > best) {
+                        best = n;
+                        best_lo = lo;
+                    }
+                }
+                if (best > 0 || rem.empty()) break;
+            }
+            if (!rem.empty() && best == 0)
+                throw std::runtime_error("offload: every outer range holds a qubit the next gates need");
+            std::vector<Operator> wg;
+            wg.reserve(rem.size());
+            for (int g : rem) {
+                Operator w = gates[g];
+                for (int &q : w.q) q = physical_to_window(q, best_lo, S, N);
+                wg.push_back(std::move(w));
+            }
+            PlanOp win;
+            win.kind = SIM_OP_WINDOW;
+            win.buffer = 0;
+            win.buffer_qubits = N;
+            win.outer_lo = best_lo;
+            win.outer_n = S;
+            win.init_window = first;
+            const size_t mark = plan.ops.size();
+            plan.ops.push_back(std::move(win));
+            const PlanStats before = plan.stats;
+            const std::vector<int> left = stages(0, W, wg, true);
+            // a window op is one pass over the whole state on the device
+            plan.stats.bytes = before.bytes + (plan.stats.bytes - before.bytes) * scale;
+            plan.stats.flops = before.flops + (plan.stats.flops - before.flops) * scale;
+            for (size_t i = mark + 1; i < plan.ops.size(); ++i) {
+                plan.ops[i].bytes *= scale;
+                plan.ops[i].flops *= scale;
+            }
+            plan.ops[mark].pass_ops = (int)(plan.ops.size() - mark - 1);
+            if (!rem.empty() && left.size() == rem.size()) throw std::runtime_error("offload: pass made no progress");
+            plan.stats.offload_passes += 1;
+            // every window is written back; all but the first pass read them first
+            plan.stats.pcie_bytes += (first ? 1.0 : 2.0) * std::ldexp(1.0, N) * amp;
+            std::vector<int> next;
+            next.reserve(left.size());
+            for (int i : left) next.push_back(rem[i]);
+            rem.swap(next);
+            first = false;
         }
     }
 
@@ -1336,13 +1457,17 @@ void build_plan(Plan &plan, const std::vector<Operator> &gates)
     const std::vector<Operator> &in = relabel ? relabelled : gates;
     Builder b{plan, plan.opt};
     std::vector<Operator> rest;
-    if (plan.opt.opt & SIM_OPT_BOOST) {
-        rest = b.booster(in);
+    if (plan.opt.window_qubits > 0) {
+        b.offload(in);
     } else {
-        b.init_op(0, plan.n);
-        rest = in;
+        if (plan.opt.opt & SIM_OPT_BOOST) {
+            rest = b.booster(in);
+        } else {
+            b.init_op(0, plan.n);
+            rest = in;
+        }
+        b.lower(0, plan.n, std::move(rest));
     }
-    b.lower(0, plan.n, std::move(rest));
     for (PlanOp &op : plan.ops)  // tables of the accumulated diagonals of the kept lowering
         for (Phase &ph : op.phases)
             for (KOp &k : ph.ops)
@@ -1359,7 +1484,8 @@ void build_plan(Plan &plan, const std::vector<Operator> &gates)
     }
     plan.stats.n_ops = plan.ops.size();
     for (const PlanOp &op : plan.ops)
-        if (op.buffer == 0) plan.stats.est_ms += 1e3 * Builder::est_seconds(op);
+        if (op.buffer == 0 && op.kind != SIM_OP_WINDOW) plan.stats.est_ms += 1e3 * Builder::est_seconds(op);
+    plan.stats.est_ms += 1e3 * plan.stats.pcie_bytes / 50e9;  // host link, one direction at a time
     auto t1 = std::chrono::steady_clock::now();
     plan.stats.plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 }

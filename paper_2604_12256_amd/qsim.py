@@ -25,7 +25,7 @@ STATUS = {0: "OK", 1: "INVAL", 2: "NOMEM", 3: "DEVICE", 4: "STATE", 5: "UNSUPPOR
 OPT_DIAG, OPT_FUSE, OPT_STAGES, OPT_BOOST, OPT_REMAP = 1, 2, 4, 8, 16
 OPT_ALL = 31
 # plan op kinds
-OP_NAMES = {0: "INIT", 1: "KRON", 2: "DENSE", 3: "DIAG", 4: "STAGE", 5: "PERM"}
+OP_NAMES = {0: "INIT", 1: "KRON", 2: "DENSE", 3: "DIAG", 4: "STAGE", 5: "PERM", 6: "WINDOW"}
 DTYPES = {"c128": 0, "c64": 1}
 
 
@@ -38,14 +38,15 @@ class SimOptions(ctypes.Structure):
     _fields_ = [("opt", ctypes.c_uint32), ("C", ctypes.c_uint32), ("F", ctypes.c_uint32),
                 ("D", ctypes.c_uint32), ("B", ctypes.c_uint32), ("force_fuse_k", ctypes.c_uint32),
                 ("L", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("dev_state", ctypes.c_void_p), ("dev_state_bytes", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("host_state", ctypes.c_void_p), ("host_state_bytes", ctypes.c_uint64)]
 
 
 class SimRunStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("n_gates", "n_ops", "full_passes", "write_passes",
                                                 "read_passes", "n_stages", "n_dense", "n_diag", "n_kron",
                                                 "n_perm", "n_subruns")] + \
-               [(f, ctypes.c_double) for f in ("plan_ms", "run_ms", "algorithmic_bytes", "flops", "est_ms")]
+               [(f, ctypes.c_double) for f in ("plan_ms", "run_ms", "algorithmic_bytes", "flops", "est_ms")] + \
+               [(f, ctypes.c_uint64) for f in ("offload_passes", "window_qubits")] + [("pcie_bytes", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -166,20 +167,28 @@ def _as_gates(gates) -> _Gates:
 
 
 def _options(opt: int, C: int, F: int, D: int, B: int, force_fuse_k: int, state_ptr: int = 0,
-             state_bytes: int = 0, stream: int = 0, L: int = 0) -> SimOptions:
+             state_bytes: int = 0, stream: int = 0, L: int = 0, host_ptr: int = 0,
+             host_bytes: int = 0) -> SimOptions:
     o = SimOptions()
     o.opt, o.C, o.F, o.D, o.B, o.force_fuse_k, o.L = opt, C, F, D, B, force_fuse_k, L
     o.dev_state = state_ptr or None
     o.dev_state_bytes = state_bytes
     o.stream = stream or None
+    o.host_state = host_ptr or None
+    o.host_state_bytes = host_bytes
     return o
 
 
 class Simulator:
-    """One state vector on the GPU and the circuit loaded into it."""
+    """One state vector on the GPU and the circuit loaded into it.
+
+    offload_window > 0 keeps the state in pinned host memory instead and
+    gives the device two windows of 2^offload_window amplitudes (host-memory
+    offload; the state may then be larger than the device memory)."""
 
     def __init__(self, n: int, dtype: str = "c128", opt: int = 0, C: int = 0, F: int = 0, D: int = 0,
-                 B: int = 0, force_fuse_k: int = 0, state=None, stream=None, device: int = 0, L: int = 0) -> None:
+                 B: int = 0, force_fuse_k: int = 0, state=None, stream=None, device: int = 0, L: int = 0,
+                 offload_window: int = 0) -> None:
         import torch
         self._lib = load_library()
         if not torch.cuda.is_available():
@@ -187,12 +196,21 @@ class Simulator:
         self.n = int(n)
         self.dtype = dtype
         real = torch.float64 if dtype == "c128" else torch.float32
+        self.host_state = None
+        host_ptr = host_bytes = 0
+        if offload_window:
+            # pinned host memory for the state, two device windows
+            self.host_state = torch.empty(2 << self.n, dtype=real, pin_memory=True)
+            host_ptr = self.host_state.data_ptr()
+            host_bytes = self.host_state.numel() * self.host_state.element_size()
+            if state is None:
+                state = torch.empty(2 * (2 << int(offload_window)), dtype=real, device=f"cuda:{device}")
         if state is None:
             state = torch.empty(2 << self.n, dtype=real, device=f"cuda:{device}")
         self.state = state
         self.stream = stream if stream is not None else torch.cuda.current_stream(state.device)
         o = _options(opt, C, F, D, B, force_fuse_k, state.data_ptr(), state.numel() * state.element_size(),
-                     self.stream.cuda_stream, L)
+                     self.stream.cuda_stream, L, host_ptr, host_bytes)
         ctx = ctypes.c_void_p()
         st = self._lib.sim_create(self.n, DTYPES[dtype], ctypes.byref(o), ctypes.byref(ctx))
         if st != OK:
@@ -313,6 +331,7 @@ class Simulator:
             self._lib.sim_destroy(self._ctx)
             self._ctx = None
         self.state = None  # the device state buffer may be released once the context is gone
+        self.host_state = None
 
     def __del__(self) -> None:
         try:
@@ -346,11 +365,18 @@ class Plan:
     """The execution plan the library builds for a circuit (no GPU needed)."""
 
     def __init__(self, n: int, gates: Sequence, dtype: str = "c128", opt: int = OPT_ALL, C: int = 0,
-                 F: int = 0, D: int = 0, B: int = 0, force_fuse_k: int = 0, L: int = 0) -> None:
+                 F: int = 0, D: int = 0, B: int = 0, force_fuse_k: int = 0, L: int = 0,
+                 offload_window: int = 0) -> None:
         self._lib = load_library()
         self.n = n
         m = _as_gates(gates)
-        o = _options(opt, C, F, D, B, force_fuse_k, L=L)
+        if offload_window:
+            # planning only: the host buffer is never touched (any non-NULL value)
+            amp = 16 if dtype == "c128" else 8
+            o = _options(opt, C, F, D, B, force_fuse_k, L=L, state_bytes=2 * amp << offload_window,
+                         host_ptr=1, host_bytes=amp << n)
+        else:
+            o = _options(opt, C, F, D, B, force_fuse_k, L=L)
         p = ctypes.c_void_p()
         st = self._lib.sim_plan_build(n, DTYPES[dtype], ctypes.byref(o), m.arr, m.n, ctypes.byref(p))
         if st != OK:
@@ -405,6 +431,9 @@ class Plan:
                 d["kernel_ops"] = kops
             elif d["kind"] == "PERM":
                 d["perm"] = [op.qubits[t] for t in range(op.nq)]
+            elif d["kind"] == "WINDOW":
+                d["outer_lo"], d["outer_n"], d["init"] = op.qubits[0], op.qubits[1], bool(op.qubits[2])
+                d["pass_ops"] = op.nq
             out.append(d)
         return out
 

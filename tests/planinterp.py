@@ -36,6 +36,13 @@ def run_plan(ops, n, layout, use_kernel_ops=True):
             v = np.zeros(1 << nb, dtype=np.complex128)
             v[0] = 1
             bufs[b] = v
+        elif kind == "WINDOW":
+            # a host-memory offload pass: its ops are exported on the full
+            # state's physical qubits, so they apply to the whole state
+            if op["init"]:
+                v = np.zeros(1 << nb, dtype=np.complex128)
+                v[0] = 1
+                bufs[b] = v
         elif kind == "KRON":
             bufs[b] = np.kron(bufs[op["src_hi"]], bufs[op["src_lo"]])
         elif kind == "DENSE":

@@ -506,3 +506,43 @@ def test_served_results_equal_solo_runs():
         else:
             assert 1 - abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real) <= 1e-6
         solo.close()
+
+
+def test_served_mix_with_large_stream_requests():
+    """Serving: 20-26-qubit requests on their own streams overlap a batch of
+    small circuits; every result equals its solo run (the large ones are
+    compared on 2^16 seeded indices and by norm, the small ones in full)."""
+    from paper_2604_12256_amd import serve as S
+    rng = np.random.default_rng(41)
+    reqs = []
+    for i in range(14):
+        n = int(rng.integers(20, 27)) if i % 3 == 0 else int(rng.integers(8, 14))
+        if i == 0:
+            n = 26                  # on its stream while the first batch runs
+        reqs.append(W.Request(i, 1e-4 * i, n, int(rng.integers(4, 12)), "c128" if i % 2 else "c64", 100 + i))
+    be = S.GpuBackend(qsim.OPT_ALL, n_streams=3, keep_states=True)
+    res = S.serve(reqs, be, max_streams=3)
+    by = {r.rid: r for r in res}
+    large = [r for r in reqs if r.n >= 20]
+    assert large and all(by[r.rid].mode == "stream" for r in large)
+    assert any(by[r.rid].mode == "batch" for r in reqs)
+    # at least one batch ran while a large request was on its stream
+    batches = [by[r.rid] for r in reqs if by[r.rid].mode == "batch"]
+    assert any(b.start < by[l.rid].done and by[l.rid].start < b.done for b in batches for l in large)
+    for req in reqs:
+        say(f"served mix rid={req.rid} n={req.n} {req.dtype} {by[req.rid].mode}")
+        solo = qsim.Simulator(req.n, dtype=req.dtype, opt=0)
+        solo.load(req.circuit())
+        solo.run()
+        a = solo.amplitudes()
+        b = be.kept[req.rid]
+        if req.n >= 20:
+            idx = W.sample_indices(req.n, 1 << 16, req.rid)
+            a, b = a[idx], b[idx]
+        if req.dtype == "c128":
+            check128(b, a, f"served rid={req.rid}")
+        else:
+            err = np.max(np.abs(a - b))
+            assert err <= 2e-5 * np.max(np.abs(a)) + 1e-7, (req.rid, err)
+        solo.close()
+

@@ -440,3 +440,66 @@ def test_fixed_low_qubits_option(oracle_mod, L):
     assert np.max(np.abs(run_plan(ops, n, p.layout(), use_kernel_ops=False) - want)) < 1e-12
     if L < 6:
         assert p.stats()["full_passes"] <= qsim.Plan(n, gates, opt=qsim.OPT_ALL, C=10, L=6).stats()["full_passes"]
+
+
+# ---------------------------------------------------------------- host-memory offload plans
+def _offload_cases(n):
+    return [("layered", W.layered(n, 8, 21)), ("mixed", W.random_mixed(n, 160, seed=22, max_k=3)),
+            ("qft", W.qft(n, 23)), ("hdiag", W.hadamard_diagonal_circuit(n, 120, 24)),
+            ("qaoa", W.qaoa_full(n, 2, 25)),
+            # controls and diagonals on the top qubits (outer bits of the windows)
+            ("controls", [Gate("H", (q,)) for q in range(n)] +
+             [Gate("CNOT", (n - 1 - (i % 3), i % (n - 3))) for i in range(3 * n)] +
+             [Gate("CPHASE", (n - 1, i), theta=0.1 * (i + 1)) for i in range(n - 1)] +
+             [Gate("RX", (n - 1,), theta=0.3), Gate("CZ", (0, n - 2))])]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_offload_plans_match_oracle(oracle_mod, dtype):
+    """Host-memory offload: each pass fixes a contiguous range of outer
+    qubits; the pass's stages (planned on the window) must reproduce the
+    oracle's state, no stage may hold an outer qubit locally, and every
+    dense operator's register qubits avoid the outer range."""
+    n = 16
+    Wq = 12 if dtype == "c128" else 13
+    for name, gates in _offload_cases(n):
+        want = oracle_mod.run(n, gates)
+        p = qsim.Plan(n, gates, dtype=dtype, opt=qsim.OPT_ALL, offload_window=Wq)
+        ops = p.ops()
+        st = p.stats()
+        assert p.layout() == list(range(n))
+        assert ops[0]["kind"] == "WINDOW" and ops[0]["init"]
+        i, passes = 0, 0
+        while i < len(ops):
+            w = ops[i]
+            assert w["kind"] == "WINDOW", (name, i, w["kind"])
+            assert w["outer_n"] == n - Wq
+            outer = set(range(w["outer_lo"], w["outer_lo"] + w["outer_n"]))
+            assert w["outer_lo"] >= (3 if dtype == "c128" else 4) and w["outer_lo"] + w["outer_n"] <= n
+            for op in ops[i + 1:i + 1 + w["pass_ops"]]:
+                assert op["kind"] in ("STAGE", "DENSE", "DIAG"), op["kind"]
+                if op["kind"] == "STAGE":
+                    assert not outer & set(op["local"]), (name, outer, op["local"])
+                    for k in op["kernel_ops"]:
+                        assert not outer & set(k["qubits"][:k["n_register"]])
+                elif op["kind"] == "DENSE":
+                    assert not outer & set(op["qubits"])
+            i += 1 + w["pass_ops"]
+            passes += 1
+        assert st["offload_passes"] == passes and st["window_qubits"] == Wq
+        amp = 16 if dtype == "c128" else 8
+        assert st["pcie_bytes"] == (2 * passes - 1) * amp * 2 ** n
+        got_k = run_plan(ops, n, p.layout())
+        got_g = run_plan(ops, n, p.layout(), use_kernel_ops=False)
+        assert np.max(np.abs(got_g - want)) < 1e-12, name
+        assert np.max(np.abs(got_k - want)) < 1e-12, name
+
+
+def test_offload_window_size_and_empty_circuit():
+    n = 16
+    p = qsim.Plan(n, [], opt=qsim.OPT_ALL, offload_window=12)
+    ops = p.ops()
+    assert [o["kind"] for o in ops] == ["WINDOW"] and ops[0]["init"] and ops[0]["pass_ops"] == 0
+    # the largest window whose two copies fit the device bytes, at most n - 1
+    assert qsim.Plan(n, [], opt=qsim.OPT_ALL, offload_window=15).stats()["window_qubits"] == 15
+    assert qsim.Plan(n, [], opt=qsim.OPT_ALL, offload_window=16).stats()["window_qubits"] == 15

@@ -307,6 +307,8 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
             // selector source bytes: a lane bit of the thread id (0x80 | bit), or
             // the physical position of a chunk or wave bit (wave-uniform)
             bool uni = true;
+            uint32_t nfield = 0;
+            std::vector<std::pair<int, int>> fields;
             for (int q : sel)
                 if (local_of[q] >= 0 && tid_bit_of_local[local_of[q]] >= 0 && tid_bit_of_local[local_of[q]] < 6)
                     uni = false;
@@ -342,13 +344,10 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
                     if (!runs.empty() && runs.back().first + runs.back().second == q) ++runs.back().second;
                     else runs.push_back({q, 1});
                 }
-                if (runs.size() <= 5) {
-                    op[10] = (uint32_t)runs.size();
-                    for (size_t r = 0; r < runs.size(); ++r)
-                        op[11 + r] = (uint32_t)runs[r].first | ((uint32_t)runs[r].second << 16);
-                }
+                if (runs.size() <= 6) nfield = (uint32_t)runs.size();
+                fields = runs;
             }
-            for (size_t t = 0; t < sel.size(); ++t) {
+            for (size_t t = 0; t < sel.size() && !nfield; ++t) {
                 const int q = sel[t];
                 uint32_t code = (uint32_t)q;
                 if (local_of[q] >= 0) {
@@ -361,10 +360,12 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
                 }
                 op[3 + t / 4] |= code << (8 * (t % 4));
             }
+            for (uint32_t f = 0; f < nfield; ++f)
+                op[3 + f] = (uint32_t)fields[f].first | ((uint32_t)fields[f].second << 16);
             const int km = __builtin_popcount(mask);
             const uint32_t shift = (k.type == qs::KOp::DENSE ? 2u * (uint32_t)km : (uint32_t)km) + amp_shift;
             op[0] = (k.type == qs::KOp::DENSE ? 1u : 2u) | (mask << 8) | ((uint32_t)sel.size() << 16) |
-                    ((uni ? 1u : 0u) << 24) | (shift << 25);
+                    (nfield << 21) | ((uni ? 1u : 0u) << 24) | (shift << 25);
             const uint64_t tbytes = toff * amp_bytes;
             op[1] = (uint32_t)tbytes;
             op[2] = (uint32_t)(tbytes >> 32);

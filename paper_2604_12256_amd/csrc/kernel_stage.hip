@@ -26,14 +26,15 @@
 //           [16 + j] LDS byte offset of register j (swizzled; j < 2^RB)
 //           [16 + 2^RB + 16 o ...] op o (a 64-byte record)
 //   op      [0] type (bits 0-7: 1 dense, 2 diagonal) | register mask (bits of the
-//           register tile the operator acts on) << 8 | selector count << 16 |
-//           selectors wave-uniform << 24 | log2 of the table bytes per selector value << 25
-//           [1,2] table byte offset   [3..9] selector sources (bytes): 0x80 | b is
-//           lane bit b of the thread id, any other value the physical position of
-//           a chunk or wave bit
-//           [10] wave-uniform selectors as bit fields: number of fields (0: read
-//           the source bytes)   [11..15] field r: first physical position |
-//           width << 16 (fields fill the selector from bit 0 up)
+//           register tile the operator acts on) << 8 | selector count << 16 (5 bits) |
+//           bit fields F << 21 (3 bits) | selectors wave-uniform << 24 |
+//           log2 of the table bytes per selector value << 25
+//           [1,2] table byte offset
+//           F = 0: [3..9] selector sources (bytes): 0x80 | b is lane bit b of the
+//           thread id, any other value the physical position of a chunk or wave bit
+//           F > 0 (wave-uniform selectors on runs of consecutive positions):
+//           [3 + f] field f: first physical position | width << 16, the fields
+//           filling the selector from bit 0 up
 //   A dense op's table holds 2^nsel matrices of (2^k)^2 entries, a diagonal
 //   op's 2^nsel blocks of 2^k factors (k = popcount of the register mask).
 #include "device.hpp"
@@ -383,18 +384,18 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
             const QS_CONST uint32_t *recs = ph + 16 + NR;
             auto apply_op = [&](const OpRec &rec, uint32_t o) __attribute__((always_inline)) {
                 const uint32_t head = rec.w[0];
-                const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0xffu, shift = head >> 25;
+                const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0x1fu, shift = head >> 25;
                 const uint64_t toff = (uint64_t)rec.w[1] | ((uint64_t)rec.w[2] << 32);
                 if ((head >> 24) & 1u) {
                     uint32_t sel;
-                    const uint32_t nfield = rec.w[10];
+                    const uint32_t nfield = (head >> 21) & 7u;
                     if (nfield) {
                         sel = 0;
                         uint32_t u = 0;
 #pragma unroll
-                        for (uint32_t f = 0; f < 5; ++f)
+                        for (uint32_t f = 0; f < 6; ++f)
                             if (f < nfield) {
-                                const uint32_t d = rec.w[11 + f], w = d >> 16;
+                                const uint32_t d = rec.w[3 + f], w = d >> 16;
                                 sel |= ((uint32_t)(ub >> (d & 63u)) & ((1u << w) - 1u)) << u;
                                 u += w;
                             }

@@ -16,7 +16,9 @@ state (16 GiB) stays resident in HBM.  Prints one JSON line:
 * precision: complex64 (and the forced 5-qubit fused-GEMM form on FP32 MFMA)
   against the complex128 GPU path at 28 and 32 qubits, time and infidelity;
 * serving: a shortened Poisson request stream through the continuous-batching
-  server and through sequential plain solves, p50/p99 latency and gate-apps/s.
+  server and through sequential plain solves, p50/p99 latency and gate-apps/s;
+* offload: the same 30-qubit circuit with its state in host memory and two
+  4 GiB device windows, gate-apps/s and host-link GB/s.
 """
 import argparse
 import json
@@ -242,6 +244,38 @@ def precision_leg():
     return rows
 
 
+def offload_leg(window=28):
+    """Host-memory offload on the 30-qubit layered circuit: the 16 GiB
+    complex128 state in pinned host memory, two device windows of 2^window
+    amplitudes; one warm-up run, then one timed run (plan + run)."""
+    import torch
+    from paper_2604_12256_amd import qsim
+    from paper_2604_12256_amd import workloads as W
+    n, gates = W.config_circuit("layered30")
+    circ = qsim.Circuit(gates)
+    log(f"[bench] offload layered30, windows of 2^{window}")
+    sim = qsim.Simulator(n, dtype="c128", opt=qsim.OPT_ALL, offload_window=window)
+    sim.load(circ)
+    sim.run()
+    log("[bench] offload warm-up done")
+    t0 = time.perf_counter()
+    sim.load(circ)
+    sim.run()
+    dt = time.perf_counter() - t0
+    st = sim.stats()
+    norm = sim.norm()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": f"layered30 complex128 (16 GiB state in pinned host memory), two device windows of "
+                        f"2^{window} amplitudes ({2 * 16 * 2 ** window / 2 ** 30:.0f} GiB of device memory)",
+            "gate_apps_per_s": round(len(gates) / dt, 1), "ms_per_step": round(dt * 1e3, 1),
+            "run_ms": round(st["run_ms"], 1), "offload_passes": st["offload_passes"],
+            "device_passes": st["full_passes"],
+            "host_link_GBps": round(st["pcie_bytes"] / (st["run_ms"] / 1e3) / 1e9, 1),
+            "norm_error": abs(norm - 1.0)}
+
+
 def serving_leg(n_requests=40, rate=0.8, seed=5):
     """A shortened serving stream: Poisson arrivals of random layered
     circuits (10..30 qubits, 10..60 layers, half complex128 and half
@@ -443,6 +477,7 @@ def main():
     ap.add_argument("--cpu-prefix", type=int, default=100)
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-offload", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--kernels", action="store_true",
                     help="print a per-kernel time / HBM-rate table at 30 qubits instead of the benchmark line")
@@ -504,6 +539,8 @@ def main():
         out["precision"] = precision_leg()
     if not args.no_serving:
         out["serving"] = serving_leg()
+    if not args.no_offload:
+        out["offload"] = offload_leg()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_prefix)

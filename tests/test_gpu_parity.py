@@ -277,6 +277,25 @@ def test_full_size_against_golden(name):
     sim.close()
 
 
+def test_layered22_full_state(oracle_mod):
+    """The 28-qubit configuration's circuit family (40 layers, seed 1) at 22
+    qubits, where the oracle's full state takes seconds: every amplitude of
+    the optimised path (booster, stages over 2^10 chunks, fusion) in both
+    precisions against it."""
+    n = 22
+    gates = W.layered(n, 40, 1)
+    say("layered22 full state (oracle)")
+    want = oracle_mod.run(n, gates)
+    for dtype in ("c128", "c64"):
+        say(f"layered22 {dtype}")
+        got, st = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_ALL)
+        assert st["n_stages"] >= 2
+        if dtype == "c128":
+            check128(got, want, "layered22")
+        else:
+            check64(got, want, oracle_mod, "layered22 c64")
+
+
 def test_diag24_full_state_and_samples(oracle_mod):
     n, gates = W.config_circuit("diag24")
     want = oracle_mod.run(n, gates)

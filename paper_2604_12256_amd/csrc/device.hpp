@@ -53,6 +53,17 @@ __device__ __forceinline__ void cmac(V &acc, V m, V a)
     acc.y = fma(m.y, a.x, acc.y);
 }
 
+// A 64-bit value every lane of the wave holds, moved to scalar registers.
+// The builtin returns a signed 32-bit int: each half is taken back as
+// unsigned before widening, so that a low half with bit 31 set (indices of
+// 2^31 and above) does not sign-extend into the high half.
+__device__ __forceinline__ uint64_t wave_uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
 // Scatter the low bits of x to the set bit positions of mask (bit-deposit).
 __device__ __forceinline__ uint64_t deposit(uint64_t x, uint64_t mask)
 {

@@ -120,22 +120,39 @@ __global__ __launch_bounds__(kBlock) void k_sample(const c2_t<R> *__restrict__ a
 
 constexpr uint32_t kZBlocks = 2048;
 
+// The sign (-1)^popcount(x & m) splits into a per-lane factor (the six lane
+// bits of x, fixed for the whole launch since the stride is a multiple of
+// 64) and a wave-uniform one (the bits above), computed once per iteration
+// in scalar registers: two FP64 operations per mask and amplitude.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_expect_z_partial(const c2_t<R> *__restrict__ a, uint64_t len, ZArgs Z,
                                                              double *__restrict__ part)
 {
     __shared__ double sh[kBlock];
-    double acc[kZMasksPerLaunch];
+    double acc[kZMasksPerLaunch], lane_sign[kZMasksPerLaunch];
+    const uint32_t lane = threadIdx.x & 63u;
 #pragma unroll
-    for (int k = 0; k < kZMasksPerLaunch; ++k) acc[k] = 0.0;
+    for (int k = 0; k < kZMasksPerLaunch; ++k) {
+        acc[k] = 0.0;
+        lane_sign[k] = (__popc(lane & (uint32_t)Z.m[k] & 63u) & 1) ? -1.0 : 1.0;
+    }
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < len; x += stride) {
-        const c2_t<R> v = a[x];
-        const double re = (double)v.x, im = (double)v.y;
-        const double p = re * re + im * im;
+    // first index of this wave's 64 consecutive amplitudes (wave-uniform)
+    uint64_t xw = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u);
+    xw = wave_uniform_u64(xw);
+    for (; xw < len; xw += stride) {
+        double p = 0.0;
+        if (xw + lane < len) {  // states below 64 amplitudes fill part of one wave
+            const c2_t<R> v = a[xw + lane];
+            const double re = (double)v.x, im = (double)v.y;
+            p = re * re + im * im;
+        }
 #pragma unroll
         for (int k = 0; k < kZMasksPerLaunch; ++k)
-            if (k < Z.nm) acc[k] += (__popcll(x & Z.m[k]) & 1) ? -p : p;
+            if (k < Z.nm) {
+                const double us = (__popcll(xw & Z.m[k]) & 1) ? -p : p;  // wave-uniform sign
+                acc[k] = fma(lane_sign[k], us, acc[k]);
+            }
     }
     for (int k = 0; k < Z.nm; ++k) {
         double v = 0.0;

@@ -155,6 +155,12 @@ def test_33q_measurement():
     m, p = sim.measure(32, 0.75)
     assert m == 1 and abs(p - 0.5) < 1e-12
     assert abs(sim.norm() - 1) < 1e-11
+    # marginals and Z strings over qubits above bit 31 after the collapse
+    # (indices of 2^31 and above on both marginal paths)
+    np.testing.assert_allclose(sim.probabilities([6, 32]), [0, 0, 0.5, 0.5], atol=1e-12)
+    np.testing.assert_allclose(sim.probabilities([32, 31]), [0, 0.5, 0, 0.5], atol=1e-12)
+    np.testing.assert_allclose(sim.probabilities([0, 32]), [0, 0, 0.5, 0.5], atol=1e-12)
+    np.testing.assert_allclose(sim.expect_z([1 << 32, (1 << 32) | (1 << 31), 1 << 31]), [-1, 0, 0], atol=1e-12)
     amp = sim.amplitudes(np.array([0, 1 << 32, (1 << n) - 1], dtype=np.uint64))
     assert abs(amp[0]) == 0 and abs(amp[1] - 2.0 ** (-(n - 1) / 2)) < 1e-15
     release(sim)

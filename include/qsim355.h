@@ -264,15 +264,21 @@ const char *sim_last_error(const sim_ctx *ctx);
 
 sim_status sim_destroy(sim_ctx *ctx);
 
-/* ---- batched small circuits (serving) --------------------------------------
- * Run several contexts whose states are small (N <= 13 for C128, N <= 14 for
- * C64) in ONE launch per 128 contexts on `stream` (NULL: the first context's
- * stream): one workgroup per circuit keeps the whole state in LDS, applies
- * the whole gate list from |0...0> and writes the final state to the
- * context's buffer.  All contexts need a loaded circuit and the same dtype
- * (SIM_E_INVAL otherwise; SIM_E_UNSUPPORTED for a state that is too large).
- * Does not wait: synchronise `stream` before reading the states.  Results
- * equal those of sim_run on each context alone, up to rounding order. */
+/* ---- batched runs (serving) -------------------------------------------------
+ * Run several loaded contexts of one dtype on `stream` (NULL: the first
+ * context's stream) with fewer, fuller launches than one sim_run each:
+ *  - small states (N <= 13 for C128, N <= 14 for C64): ONE launch per 128
+ *    contexts, one workgroup per circuit keeping the whole state in LDS
+ *    (applies the whole gate list from |0...0> and writes the final state);
+ *  - every other resident state: its plan's ops run in order on `stream`,
+ *    and the full-state cache-blocked stages (Alg. 2) of all waiting states
+ *    with the same chunk size go out together, up to 64 states per launch,
+ *    one workgroup per chunk; each chunk is computed exactly as by the
+ *    state's own stage launch, so results are bitwise those of sim_run.
+ * Contexts must be distinct and loaded (SIM_E_STATE otherwise) and share the
+ * dtype (SIM_E_INVAL); host-memory offload contexts are SIM_E_UNSUPPORTED.
+ * Does not wait: synchronise `stream` before reading the states.  Small
+ * states equal those of sim_run up to rounding order. */
 sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream);
 
 /* ---- host-only planning (no device needed) --------------------------------

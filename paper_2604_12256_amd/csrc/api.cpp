@@ -665,68 +665,121 @@ sim_status execute_offload(sim_ctx *c)
     return SIM_OK;
 }
 
+// One prepared op of a resident-state plan on stream st.  hipErrorNotSupported
+// marks an op kind this path does not execute.
+template <typename R>
+hipError_t launch_op(sim_ctx *c, size_t i, hipStream_t st)
+{
+    const size_t amp = c->amp_bytes();
+    const Prepared &p = c->prep[i];
+    switch (p.kind) {
+    case SIM_OP_INIT:
+        return qs::launch_init<R>(c->buf(p.buffer), p.nb, st);
+    case SIM_OP_KRON: {
+        const int nlo = c->plan.buffer_qubits[p.lo], nhi = c->plan.buffer_qubits[p.hi];
+        return qs::launch_kron<R>(c->buf(p.buffer), c->buf(p.lo), nlo, c->buf(p.hi), nhi, st);
+    }
+    case SIM_OP_DENSE:
+        if (p.mfma)
+            return qs::launch_dense_mfma<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp,
+                                            st);
+        return qs::launch_dense<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp, st);
+    case SIM_OP_PERM:
+        return qs::launch_swap_bits<R>(c->buf(p.buffer), p.nb, p.plo, p.phi, p.npairs, st);
+    case SIM_OP_DIAG:
+        return qs::launch_diag_q<R>(c->buf(p.buffer), p.nb, (int)p.gd.k, p.gd.q,
+                                    (const char *)c->tables.p + p.gd.table * amp, st);
+    case SIM_OP_STAGE:
+        if (p.small) {
+            if (!p.batch) return hipSuccess;  // launched with the first op of its batch
+            uint32_t maxn = 0;
+            for (uint32_t u = 0; u < p.batch; ++u) maxn = std::max<uint32_t>(maxn, c->prep[i + u].nb);
+            return qs::launch_small_batch<R>((const qs::SmallItem *)c->items.p + p.item, p.batch, maxn, st);
+        } else {
+            qs::StageLaunch L;
+            L.state = c->buf(p.buffer);
+            L.prog = (const uint32_t *)c->prog.p + p.prog_off;
+            L.tables = c->tables.p;
+            L.n = p.nb;
+            L.C = p.C;
+            L.nphases = p.nph;
+            L.nchunks = p.nchunks;
+            return qs::launch_stage<R>(L, st);
+        }
+    default:
+        return hipErrorNotSupported;
+    }
+}
+
 template <typename R>
 sim_status execute(sim_ctx *c)
 {
     if (c->window) return execute_offload<R>(c);
-    const size_t amp = c->amp_bytes();
-    const R *unused = nullptr;
-    (void)unused;
     for (size_t i = 0; i < c->prep.size(); ++i) {
-        const Prepared &p = c->prep[i];
-        hipError_t e = hipSuccess;
         if (c->profiling) HIPCHK(c, hipEventRecord(c->op_ev[2 * i], c->stream), "event record");
-        switch (p.kind) {
-        case SIM_OP_INIT:
-            e = qs::launch_init<R>(c->buf(p.buffer), p.nb, c->stream);
-            break;
-        case SIM_OP_KRON: {
-            const int nlo = c->plan.buffer_qubits[p.lo], nhi = c->plan.buffer_qubits[p.hi];
-            e = qs::launch_kron<R>(c->buf(p.buffer), c->buf(p.lo), nlo, c->buf(p.hi), nhi, c->stream);
-            break;
-        }
-        case SIM_OP_DENSE:
-            if (p.mfma)
-                e = qs::launch_dense_mfma<R>(c->buf(p.buffer), p.nb, p.gd,
-                                             (const char *)c->tables.p + p.gd.table * amp, c->stream);
-            else
-                e = qs::launch_dense<R>(c->buf(p.buffer), p.nb, p.gd, (const char *)c->tables.p + p.gd.table * amp,
-                                        c->stream);
-            break;
-        case SIM_OP_PERM:
-            e = qs::launch_swap_bits<R>(c->buf(p.buffer), p.nb, p.plo, p.phi, p.npairs, c->stream);
-            break;
-        case SIM_OP_DIAG:
-            e = qs::launch_diag_q<R>(c->buf(p.buffer), p.nb, (int)p.gd.k, p.gd.q,
-                                     (const char *)c->tables.p + p.gd.table * amp, c->stream);
-            break;
-        case SIM_OP_STAGE:
-            if (p.small) {
-                if (p.batch) {
-                    uint32_t maxn = 0;
-                    for (uint32_t u = 0; u < p.batch; ++u) maxn = std::max<uint32_t>(maxn, c->prep[i + u].nb);
-                    e = qs::launch_small_batch<R>((const qs::SmallItem *)c->items.p + p.item, p.batch, maxn,
-                                                  c->stream);
-                }
-            } else {
-                qs::StageLaunch L;
-                L.state = c->buf(p.buffer);
-                L.prog = (const uint32_t *)c->prog.p + p.prog_off;
-                L.tables = c->tables.p;
-                L.n = p.nb;
-                L.C = p.C;
-                L.nphases = p.nph;
-                L.nchunks = p.nchunks;
-                e = qs::launch_stage<R>(L, c->stream);
-            }
-            break;
-        default:
-            return fail(c, SIM_E_UNSUPPORTED, "plan op kind not executable");
-        }
+        const hipError_t e = launch_op<R>(c, i, c->stream);
+        if (e == hipErrorNotSupported) return fail(c, SIM_E_UNSUPPORTED, "plan op kind not executable");
         if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
         if (c->profiling) HIPCHK(c, hipEventRecord(c->op_ev[2 * i + 1], c->stream), "event record");
     }
     return SIM_OK;
+}
+
+// Several resident-state plans on one stream, their full-state stages
+// launched together: every state runs its ops one by one up to its next
+// full-state stage; then the states waiting at a stage (grouped by chunk
+// size, up to 64 per launch) run that stage in one launch, one workgroup per
+// chunk.  Every chunk computes exactly what the state's own stage launch
+// computes for it.
+template <typename R>
+sim_status execute_staged_batch(sim_ctx *const *cs, uint32_t n, hipStream_t st)
+{
+    std::vector<size_t> cur(n, 0);
+    auto batched = [](const Prepared &p) { return p.kind == SIM_OP_STAGE && !p.small && p.buffer == 0; };
+    for (;;) {
+        bool left = false;
+        for (uint32_t k = 0; k < n; ++k) {
+            sim_ctx *c = cs[k];
+            while (cur[k] < c->prep.size() && !batched(c->prep[cur[k]])) {
+                const hipError_t e = launch_op<R>(c, cur[k], st);
+                if (e == hipErrorNotSupported) return fail(c, SIM_E_UNSUPPORTED, "plan op kind not executable");
+                if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+                ++cur[k];
+            }
+            left |= cur[k] < c->prep.size();
+        }
+        if (!left) return SIM_OK;
+        // states waiting at a full-state stage, by chunk size
+        std::vector<uint32_t> wait;
+        for (uint32_t k = 0; k < n; ++k)
+            if (cur[k] < cs[k]->prep.size()) wait.push_back(k);
+        std::stable_sort(wait.begin(), wait.end(), [&](uint32_t a, uint32_t b) {
+            return cs[a]->prep[cur[a]].C < cs[b]->prep[cur[b]].C;
+        });
+        for (size_t w0 = 0; w0 < wait.size();) {
+            const int C = cs[wait[w0]]->prep[cur[wait[w0]]].C;
+            qs::StageJobs J{};
+            size_t w = w0;
+            uint64_t blocks = 0;
+            while (w < wait.size() && J.n < qs::kStageJobsMax) {
+                sim_ctx *c = cs[wait[w]];
+                const Prepared &p = c->prep[cur[wait[w]]];
+                if (p.C != C || blocks + p.nchunks > 0x7fffffffull) break;
+                J.first_block[J.n] = (uint32_t)blocks;
+                J.job[J.n].state = c->buf(0);
+                J.job[J.n].prog = (const uint32_t *)c->prog.p + p.prog_off;
+                J.job[J.n].tables = c->tables.p;
+                blocks += p.nchunks;
+                ++J.n;
+                ++w;
+            }
+            J.first_block[J.n] = (uint32_t)blocks;
+            const hipError_t e = qs::launch_stage_multi<R>(J, C, st);
+            if (e != hipSuccess) return hip_fail(cs[wait[w0]], e, "batched stage launch");
+            for (size_t u = w0; u < w; ++u) ++cur[wait[u]];
+            w0 = w;
+        }
+    }
 }
 
 void fill_stats(const qs::Plan &P, uint64_t n_gates, sim_run_stats *s)
@@ -1386,16 +1439,20 @@ sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream)
         sim_ctx *c = ctxs[i];
         if (!c) return SIM_E_INVAL;
         if (!c->loaded) return fail(c, SIM_E_STATE, "no circuit loaded");
-        if (!c->small_whole) return fail(c, SIM_E_UNSUPPORTED, "state too large for a batched small-state run");
+        if (c->window) return fail(c, SIM_E_UNSUPPORTED, "host-memory offload contexts cannot be batched");
         if (c->dtype != ctxs[0]->dtype) return fail(c, SIM_E_INVAL, "batched contexts must share the dtype");
+        for (uint32_t j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(c, SIM_E_INVAL, "a context appears twice in the batch");
     }
     hipStream_t s = stream ? (hipStream_t)stream : ctxs[0]->stream;
-    for (uint32_t i0 = 0; i0 < n_ctx; i0 += qs::kSmallBatchMax) {
-        const uint32_t cnt = std::min<uint32_t>(qs::kSmallBatchMax, n_ctx - i0);
+    std::vector<sim_ctx *> small, staged;
+    for (uint32_t i = 0; i < n_ctx; ++i) (ctxs[i]->small_whole ? small : staged).push_back(ctxs[i]);
+    for (size_t i0 = 0; i0 < small.size(); i0 += qs::kSmallBatchMax) {
+        const uint32_t cnt = (uint32_t)std::min<size_t>(qs::kSmallBatchMax, small.size() - i0);
         qs::SmallPtrs P{};
         uint32_t maxn = 0;
         for (uint32_t u = 0; u < cnt; ++u) {
-            sim_ctx *c = ctxs[i0 + u];
+            sim_ctx *c = small[i0 + u];
             P.item[u] = (const qs::SmallItem *)c->items.p + c->small_whole_item;
             maxn = std::max<uint32_t>(maxn, (uint32_t)c->n);
         }
@@ -1403,11 +1460,21 @@ sim_status sim_run_batch(sim_ctx *const *ctxs, uint32_t n_ctx, void *stream)
                                                   : qs::launch_small_ptrs<float>(P, cnt, maxn, s);
         if (e != hipSuccess) return hip_fail(ctxs[0], e, "batched launch");
     }
+    if (!staged.empty()) {
+        const sim_status st = ctxs[0]->dtype == SIM_C128
+                                  ? execute_staged_batch<double>(staged.data(), (uint32_t)staged.size(), s)
+                                  : execute_staged_batch<float>(staged.data(), (uint32_t)staged.size(), s);
+        if (st != SIM_OK) return st;
+    }
+    for (sim_ctx *c : small) {
+        c->layout.resize(c->n);
+        for (int q = 0; q < c->n; ++q) c->layout[q] = q;
+    }
+    for (sim_ctx *c : staged) c->layout = c->plan.layout;
     for (uint32_t i = 0; i < n_ctx; ++i) {
         ctxs[i]->ran = true;
         ctxs[i]->timing_pending = false;
-        ctxs[i]->layout.resize(ctxs[i]->n);
-        for (int q = 0; q < ctxs[i]->n; ++q) ctxs[i]->layout[q] = q;
+        ctxs[i]->profiled = false;
     }
     return SIM_OK;
 }

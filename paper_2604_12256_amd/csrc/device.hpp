@@ -162,6 +162,23 @@ struct StageLaunch {
 };
 template <typename R> hipError_t launch_stage(const StageLaunch &L, hipStream_t s);
 
+// One stage of each of several independent states in one launch (kernel
+// argument, so no device allocation): job j owns workgroups
+// first_block[j] .. first_block[j + 1] - 1, one chunk each.  Every job's
+// program uses the launch's chunk size C and has nchunks = its block count.
+constexpr uint32_t kStageJobsMax = 64;
+struct StageJob {
+    void *state;
+    const uint32_t *prog;
+    const void *tables;
+};
+struct StageJobs {
+    uint32_t n;
+    uint32_t first_block[kStageJobsMax + 1];
+    StageJob job[kStageJobsMax];
+};
+template <typename R> hipError_t launch_stage_multi(const StageJobs &J, int C, hipStream_t s);
+
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
 // host-memory offload: window v (outer qubits fixed) between the mapped host
 // state and a device window; rows of row_bytes, 2^S windows interleaved

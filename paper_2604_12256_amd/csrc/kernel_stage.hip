@@ -307,11 +307,11 @@ __device__ __forceinline__ void transpose(c2_t<R> *amp, uint32_t lds_base, uint3
     }
 }
 
+// The chunks first, first + step, ... below nchunks of one stage program.
 template <typename R, int RB>
-__global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
-                                                            const uint32_t *__restrict__ Pg,
-                                                            const c2_t<R> *__restrict__ tables,
-                                                            uint64_t nchunks, uint64_t xbits)
+__device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const uint32_t *__restrict__ Pg,
+                                             const c2_t<R> *__restrict__ tables, uint64_t first, uint64_t nchunks,
+                                             uint64_t step, uint64_t xbits)
 {
     using V = c2_t<R>;
     const QS_CONST uint32_t *P = as_const(Pg);
@@ -347,10 +347,9 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     // chunk bits at their physical positions: deposited once, then advanced
     // by a masked add (the bits outside the mask are set, so that carries run
     // through them)
-    const uint64_t cstep = deposit(gridDim.x, Gmask);
-    uint64_t cbase = deposit(blockIdx.x, Gmask);
-    for (uint64_t chunk = blockIdx.x; chunk < nchunks;
-         chunk += gridDim.x, cbase = ((cbase | ~Gmask) + cstep) & Gmask) {
+    const uint64_t cstep = deposit(step, Gmask);
+    uint64_t cbase = deposit(first, Gmask);
+    for (uint64_t chunk = first; chunk < nchunks; chunk += step, cbase = ((cbase | ~Gmask) + cstep) & Gmask) {
         // chunk bits, thread bits and register bits are disjoint: each
         // amplitude is a per-thread pointer plus a wave-uniform offset
         V *const pt = state + (cbase | tphys);
@@ -429,6 +428,33 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
     }
 }
 
+template <typename R, int RB>
+__global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
+                                                            const uint32_t *__restrict__ Pg,
+                                                            const c2_t<R> *__restrict__ tables,
+                                                            uint64_t nchunks, uint64_t xbits)
+{
+    stage_chunks<R, RB>(state, Pg, tables, blockIdx.x, nchunks, gridDim.x, xbits);
+}
+
+// Stages of several independent states (one stage program each, same chunk
+// size) in one launch: workgroup b runs chunk b - first_block[j] of job j,
+// where job j is the last with first_block[j] <= b.
+template <typename R, int RB>
+__global__ __launch_bounds__(kStageMaxThreads) void k_stage_multi(const StageJobs J)
+{
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = J.n;  // first_block[lo] <= b < first_block[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (J.first_block[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const StageJob &job = J.job[lo];
+    const uint64_t chunk = b - J.first_block[lo];
+    stage_chunks<R, RB>((c2_t<R> *)job.state, job.prog, (const c2_t<R> *)job.tables, chunk, chunk + 1, 1, 0);
+}
+
 }  // namespace
 
 template <typename R>
@@ -458,7 +484,32 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_stage_multi(const StageJobs &J, int C, hipStream_t s)
+{
+    constexpr int RB = sizeof(R) == 8 ? 4 : 5;
+    if (C < RB + 6 || C > 16 || J.n == 0 || J.n > kStageJobsMax) return hipErrorInvalidValue;
+    const uint32_t threads = 1u << (C - RB);
+    const uint32_t lds = (uint32_t)sizeof(c2_t<R>) << C;
+    if (threads > (uint32_t)kStageMaxThreads || lds > kStageLdsBytes) return hipErrorInvalidValue;
+    for (uint32_t j = 0; j < J.n; ++j)
+        if (J.first_block[j + 1] <= J.first_block[j] || J.job[j].state == nullptr || J.job[j].prog == nullptr)
+            return hipErrorInvalidValue;
+    if (J.first_block[0] != 0) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_stage_multi<R, RB>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageLdsBytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    k_stage_multi<R, RB><<<J.first_block[J.n], threads, lds, s>>>(J);
+    return hipGetLastError();
+}
+
 template hipError_t launch_stage<double>(const StageLaunch &, hipStream_t);
 template hipError_t launch_stage<float>(const StageLaunch &, hipStream_t);
+template hipError_t launch_stage_multi<double>(const StageJobs &, int, hipStream_t);
+template hipError_t launch_stage_multi<float>(const StageJobs &, int, hipStream_t);
 
 }  // namespace qs

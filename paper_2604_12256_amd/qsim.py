@@ -352,7 +352,10 @@ def device_copy(dst, src, stream=None) -> None:
 
 
 def run_batch(sims: Sequence[Simulator], stream=None) -> None:
-    """One launch for several small circuits (each must have a loaded circuit)."""
+    """Runs several loaded circuits of one dtype together: small states in
+    one launch per 128, larger resident states with their full-state stages
+    launched together (one launch per stage step for up to 64 states).
+    Does not wait: synchronise the stream before reading the states."""
     lib = load_library()
     arr = (ctypes.c_void_p * max(1, len(sims)))(*[s._ctx for s in sims])
     st = lib.sim_run_batch(arr, len(sims), stream.cuda_stream if stream is not None else None)

@@ -16,9 +16,10 @@ Requests (circuits of 10..30 qubits) arrive over time.  The server
   are still admitted;
 * runs every admitted large circuit on a stream of its own (plan on the
   host, then the optimised plan on the device), overlapping on the GPU;
-* collects admitted small circuits (whole state fits one workgroup's LDS)
-  and runs all pending ones in one batched launch whenever the batch stream
-  is idle;
+* collects admitted small and mid-size circuits (up to BATCH_MAX qubits)
+  and runs all pending ones together whenever the batch stream is idle:
+  states that fit one workgroup's LDS in one launch, the others with their
+  full-state stages launched together (one launch per stage step);
 * detects completion by polling stream events, records latency =
   completion - arrival, and releases the memory, which admits more requests.
 
@@ -44,7 +45,8 @@ import numpy as np
 from . import workloads as W
 
 AMP_BYTES = {"c128": 16, "c64": 8}
-SMALL_MAX = {"c128": 13, "c64": 14}
+SMALL_MAX = {"c128": 13, "c64": 14}   # whole state in one workgroup's LDS
+BATCH_MAX = {"c128": 18, "c64": 19}   # run in the batch rather than on a stream of their own
 
 
 @dataclass
@@ -69,6 +71,10 @@ def state_bytes(n: int, dtype: str) -> int:
 
 def is_small(n: int, dtype: str) -> bool:
     return n <= SMALL_MAX[dtype]
+
+
+def is_batched(n: int, dtype: str) -> bool:
+    return n <= BATCH_MAX[dtype]
 
 
 def reserve_bytes(n: int, dtype: str) -> int:
@@ -173,7 +179,7 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
     used = 0
     free_streams = list(range(max_streams))
     running: List[_Slot] = []          # large circuits on their own streams
-    small_ready: List[_Slot] = []      # admitted small circuits waiting for the batch
+    small_ready: List[_Slot] = []      # admitted batched circuits waiting for the batch
     batch: Optional[List[_Slot]] = None
     batch_token = None
     bypassed = 0
@@ -191,7 +197,7 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
         head_mem = head_stream = False   # what a blocked head request waits for
         while i < len(queue):
             req = queue[i]
-            small = is_small(req.n, req.dtype)
+            small = is_batched(req.n, req.dtype)   # runs in the batch: takes no stream
             need = reserve_bytes(req.n, req.dtype)
             mem_ok = used + need <= budget
             stream_ok = small or bool(free_streams)
@@ -233,7 +239,7 @@ def serve(requests: Sequence[W.Request], backend, max_streams: int = 4, max_bypa
                 res.mode = "stream"
                 running.append(slot)
             progressed = True
-        # one batched launch for every admitted small circuit when idle
+        # one batched run of every admitted batched circuit when idle
         if batch is None and small_ready:
             batch, small_ready = small_ready, []
             t = backend.now()

@@ -394,6 +394,70 @@ def test_batched_small_circuits(oracle_mod):
         sim.close()
 
 
+def test_batched_mid_size_circuits_staged(oracle_mod):
+    """States above the small-state limit in one batch: their full-state
+    stages go out together (one launch per stage step, one workgroup per
+    chunk), with small circuits in the same call.  Each state is bitwise its
+    solo run, and equals the oracle where the oracle is cheap."""
+    import torch
+    cases = []
+    for i, (n, dt) in enumerate([(14, "c128"), (15, "c128"), (16, "c128"), (17, "c128"), (14, "c128"),
+                                 (18, "c128"), (12, "c128"), (20, "c128")]):
+        gates = W.layered(n, 6 + i % 4, seed=300 + i) + W.random_mixed(n, 30, seed=400 + i, max_k=3)
+        sim = qsim.Simulator(n, dtype=dt, opt=qsim.OPT_ALL)
+        sim.load(gates)
+        cases.append((n, gates, sim))
+    say("staged batch: 8 complex128 states of 12..20 qubits")
+    qsim.run_batch([c[2] for c in cases])
+    torch.cuda.synchronize()
+    got = [c[2].amplitudes() for c in cases]
+    for (n, gates, sim), g in zip(cases, got):
+        if n <= 16:
+            check128(g, oracle_mod.run(n, gates), f"staged batch n={n}")
+        sim.run()
+        solo = sim.amplitudes()
+        if n > qsim_small_max("c128"):
+            assert np.array_equal(solo, g), f"staged batch n={n} differs from its solo run"
+        else:
+            check128(g, solo, f"small n={n}")
+        sim.close()
+    # complex64, and a batch with more states than one launch holds
+    sims = []
+    for i in range(70):
+        n = 15 + i % 3
+        sim = qsim.Simulator(n, dtype="c64", opt=qsim.OPT_ALL)
+        sim.load(W.layered(n, 3 + i % 3, seed=500 + i))
+        sims.append(sim)
+    say("staged batch: 70 complex64 states of 15..17 qubits")
+    qsim.run_batch(sims)
+    torch.cuda.synchronize()
+    got = [s.amplitudes() for s in sims]
+    for sim, g in zip(sims, got):
+        sim.run()
+        assert np.array_equal(sim.amplitudes(), g), f"staged batch c64 n={sim.n}"
+        sim.close()
+
+
+def qsim_small_max(dtype):
+    return 13 if dtype == "c128" else 14
+
+
+def test_batch_rejects_duplicates_and_mixed_dtypes():
+    a = qsim.Simulator(15, opt=qsim.OPT_ALL)
+    b = qsim.Simulator(15, dtype="c64", opt=qsim.OPT_ALL)
+    a.load(W.layered(15, 2, seed=1))
+    b.load(W.layered(15, 2, seed=2))
+    with pytest.raises(qsim.QsimError):
+        qsim.run_batch([a, a])
+    with pytest.raises(qsim.QsimError):
+        qsim.run_batch([a, b])
+    c = qsim.Simulator(15, opt=qsim.OPT_ALL)  # nothing loaded
+    with pytest.raises(qsim.QsimError):
+        qsim.run_batch([a, c])
+    for s in (a, b, c):
+        s.close()
+
+
 def test_ghz_30q_closed_form():
     """GHZ at 30 qubits: exactly two amplitudes of 1/sqrt(2)."""
     n = 30
@@ -509,7 +573,7 @@ def test_served_results_equal_solo_runs():
     """Serving loop: every request's final state equals its solo run (batched
     small circuits and overlapping large ones)."""
     from paper_2604_12256_amd import serve as S
-    reqs = W.serving_stream(24, 500.0, 7, n_min=8, n_max=18)
+    reqs = W.serving_stream(24, 500.0, 7, n_min=8, n_max=22)
     be = S.GpuBackend(qsim.OPT_ALL, n_streams=3, keep_states=True)
     res = S.serve(reqs, be, max_streams=3)
     assert sorted(r.rid for r in res) == sorted(r.rid for r in reqs)

@@ -77,10 +77,19 @@ def test_small_circuits_are_batched():
     reqs = stream(n_req=80, rate=20000.0, n_min=10, n_max=14)
     be = FakeBackend(budget=1 << 34)
     res = S.serve(reqs, be)
-    small = [r for r in res if r.n <= S.SMALL_MAX[r.dtype]]
+    small = [r for r in res if r.n <= S.BATCH_MAX[r.dtype]]
     assert small and all(r.mode == "batch" for r in small)
     assert max(len(b) for b in be.batches) > 1          # several circuits in one launch
     assert sum(len(b) for b in be.batches) == len(small)
+
+
+def test_mid_size_circuits_join_the_batch_large_ones_take_streams():
+    reqs = [W.Request(0, 0.0, 16, 10, "c128", 1), W.Request(1, 0.0, 18, 10, "c128", 2),
+            W.Request(2, 0.0, 19, 10, "c64", 3), W.Request(3, 0.0, 19, 10, "c128", 4),
+            W.Request(4, 0.0, 20, 10, "c64", 5)]
+    be = FakeBackend(budget=1 << 34)
+    res = {r.rid: r for r in S.serve(reqs, be)}
+    assert [res[i].mode for i in range(5)] == ["batch", "batch", "batch", "stream", "stream"]
 
 
 def test_admission_respects_memory_budget():

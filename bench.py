@@ -297,7 +297,50 @@ def serving_leg(n_requests=40, rate=0.8, seed=5):
     return {"stream": f"{n_requests} requests, Poisson rate {rate}/s, seed {seed}, 10..30 qubits, 10..60 layers, "
                       f"half complex128",
             "served": {k: round(served[k], 4) if isinstance(served[k], float) else served[k] for k in keep},
-            "sequential_plain": {k: round(plain[k], 4) if isinstance(plain[k], float) else plain[k] for k in keep}}
+            "sequential_plain": {k: round(plain[k], 4) if isinstance(plain[k], float) else plain[k] for k in keep},
+            "mid_size_batch": mid_size_batch()}
+
+
+def mid_size_batch(count=48, n=16, layers=20, seed=60):
+    """Device time of `count` planned 16-qubit layered circuits (complex128):
+    one after the other on one stream (sim_run_async each) against one
+    staged batch (sim_run_batch: their full-state stages in shared launches).
+    Plans are built before the clock starts; best of three."""
+    import torch
+    from paper_2604_12256_amd import qsim
+    from paper_2604_12256_amd import workloads as W
+    stream = torch.cuda.Stream()
+    sims = []
+    for i in range(count):
+        sim = qsim.Simulator(n, opt=qsim.OPT_ALL, stream=stream)
+        sim.load(W.layered(n, layers, seed + i))
+        sims.append(sim)
+
+    def timed(fn):
+        best = 1e9
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            stream.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    def solo():
+        for sim in sims:
+            sim.run_async()
+
+    solo_ms = timed(solo)
+    batch_ms = timed(lambda: qsim.run_batch(sims, stream=stream))
+    stages = sims[0].stats()["n_stages"]
+    for sim in sims:
+        sim.close()
+    gates = count * W.layered_gate_count(n, layers)
+    return {"circuits": count, "qubits": n, "layers": layers, "dtype": "c128", "stages_each": stages,
+            "one_by_one_ms": round(solo_ms, 3), "staged_batch_ms": round(batch_ms, 3),
+            "one_by_one_gate_apps_per_s": round(gates / solo_ms * 1e3, 1),
+            "staged_batch_gate_apps_per_s": round(gates / batch_ms * 1e3, 1)}
 
 
 def kernel_table(n=30):

@@ -64,9 +64,10 @@ __global__ __launch_bounds__(kMfmaThreads) void k_dense_mfma(c2_t<R> *__restrict
             if ((c >> t) & 1) o |= 1ull << g.q[t];
         return o;
     };
-    uint64_t in_off[S];   // B row 4s + q -> amplitude 2s + q/2, part q%2
-#pragma unroll
-    for (int s = 0; s < S; ++s) in_off[s] = off(2 * s + (int)(q >> 1));
+    // B row 4s + q is part q%2 of amplitude 2s + q/2: a wave-uniform offset
+    // (matrix index 2s) plus the lane's bit for q/2 (gate qubit 0); offsets
+    // count scalar parts (R), so a lane loads only the part it uses.
+    const uint64_t lane_in = ((uint64_t)(q >> 1) << g.q[0]) * 2 + (q & 1);
     // Output amplitudes written by this lane, two per tile:
     //  rows 16t + 4q + v (FP32): amplitudes 8t + 2q + {0, 1}, (re, im) = (v0, v1), (v2, v3);
     //  rows 16t + 4v + q (FP64): lane holds re (q even) or im (q odd) of amplitudes
@@ -85,16 +86,23 @@ __global__ __launch_bounds__(kMfmaThreads) void k_dense_mfma(c2_t<R> *__restrict
         }
     }
 
+    const R *ap = reinterpret_cast<const R *>(a);
+    auto load_b = [&](uint64_t bb, R *bv) {
+        const uint64_t base2 = insert_zeros<K>(bb * 16 + j, g.sorted) * 2 + lane_in;
+#pragma unroll
+        for (int s = 0; s < S; ++s) bv[s] = ap[base2 + off(2 * s) * 2];
+    };
     const uint64_t wave = ((uint64_t)blockIdx.x * kMfmaThreads + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kMfmaThreads) >> 6;
+    // the next batch's operands are loaded while this batch's products run
+    constexpr bool kPrefetch = true;
+    R bv[S], bn[S];
+    if (wave < nbatches) load_b(wave, bv);
     for (uint64_t b = wave; b < nbatches; b += nwaves) {
-        const uint64_t base = insert_zeros<K>(b * 16 + j, g.sorted);
-        R bv[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const V v = a[base | in_off[s]];
-            bv[s] = (q & 1) ? v.y : v.x;
+        if constexpr (kPrefetch) {
+            if (b + nwaves < nbatches) load_b(b + nwaves, bn);
         }
+        const uint64_t base = insert_zeros<K>(b * 16 + j, g.sorted);
         acc_t acc[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -131,6 +139,12 @@ __global__ __launch_bounds__(kMfmaThreads) void k_dense_mfma(c2_t<R> *__restrict
             }
             a[base | out_off[t][0]] = y0;
             a[base | out_off[t][1]] = y1;
+        }
+        if constexpr (kPrefetch) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) bv[s] = bn[s];
+        } else if (b + nwaves < nbatches) {
+            load_b(b + nwaves, bv);
         }
     }
 }

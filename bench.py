@@ -396,7 +396,8 @@ def kernel_table(n=30):
         add("k_init", "|0...0>", op_ms([], 0, "INIT"), state_bytes)
         for k in (1, 2, 3):
             g = [Gate("U", tuple(range(7, 7 + k)), data=W.haar_unitary(rng, 1 << k))]
-            add("k_dense", f"dense k={k} (qubits 7..)", op_ms(g, 0, "DENSE"), 2 * state_bytes)
+            kern = "k_dense_mfma" if (k == 3 and dtype == "c64") else "k_dense"   # FP32 MFMA from k = 3
+            add(kern, f"dense k={k} (qubits 7..)", op_ms(g, 0, "DENSE"), 2 * state_bytes)
         for k in (4, 5):
             g = [Gate("U", tuple(range(7, 7 + k)), data=W.haar_unitary(rng, 1 << k))]
             add("k_dense_mfma", f"dense k={k} (qubits 7..)", op_ms(g, 0, "DENSE"), 2 * state_bytes)

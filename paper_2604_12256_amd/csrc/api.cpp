@@ -432,7 +432,10 @@ sim_status prepare(sim_ctx *c)
         case SIM_OP_DIAG: {
             const uint64_t toff = tables.size();
             const int k = op.op.k();
-            if (!op.op.diag && (k == 4 || k == 5) && op.buffer_qubits >= k + 4) {
+            // fused gates on the matrix cores from k = 4 (FP64) / k = 3 (FP32;
+            // the FP64 three-qubit gate measured faster on the VALU kernel)
+            const int kmin = c->dtype == SIM_C64 ? 3 : 4;
+            if (!op.op.diag && k >= kmin && k <= 5 && op.buffer_qubits >= k + 4) {
                 // real-ified 2^(k+1) x 2^(k+1) matrix for the MFMA kernel,
                 // stored as consecutive pairs of reals
                 const int d = 1 << k, D = 2 * d;

@@ -1,4 +1,4 @@
-// Dense k-qubit gate (k = 4, 5) on the matrix cores: a batched GEMM.
+// Dense k-qubit gate (k = 3, 4, 5) on the matrix cores: a batched GEMM.
 //
 // For every group of 2^k amplitudes that differ only in the gate's qubits
 // (Sec. 2.2), y = U x.  Written in real arithmetic on interleaved (re, im)
@@ -155,14 +155,15 @@ template <typename R>
 hipError_t launch_dense_mfma(void *state, int n, const GateDesc &g, const void *mat, hipStream_t s)
 {
     const int k = (int)g.k;
-    if ((k != 4 && k != 5) || n < k + 4) return hipErrorInvalidValue;
+    if (k < 3 || k > 5 || n < k + 4) return hipErrorInvalidValue;
     const uint64_t nbatches = 1ull << (n - k - 4);
     const uint64_t waves_per_block = kMfmaThreads / 64;
     uint64_t blocks = (nbatches + waves_per_block - 1) / waves_per_block;
     if (blocks > 8192) blocks = 8192;
     auto *a = (c2_t<R> *)state;
     auto *m = (const R *)mat;
-    if (k == 4) k_dense_mfma<R, 4><<<(uint32_t)blocks, kMfmaThreads, 0, s>>>(a, m, nbatches, g);
+    if (k == 3) k_dense_mfma<R, 3><<<(uint32_t)blocks, kMfmaThreads, 0, s>>>(a, m, nbatches, g);
+    else if (k == 4) k_dense_mfma<R, 4><<<(uint32_t)blocks, kMfmaThreads, 0, s>>>(a, m, nbatches, g);
     else k_dense_mfma<R, 5><<<(uint32_t)blocks, kMfmaThreads, 0, s>>>(a, m, nbatches, g);
     return hipGetLastError();
 }

@@ -137,9 +137,9 @@ def test_complex64_paths(oracle_mod):
             check64(got, want, oracle_mod, f"c64 n={n} opt={opt}")
 
 
-@pytest.mark.parametrize("k", [4, 5])
+@pytest.mark.parametrize("k", [3, 4, 5])
 def test_forced_fusion_mfma(oracle_mod, k):
-    """Fused 4- and 5-qubit gates run as batched GEMMs on the matrix cores."""
+    """Fused 3-, 4- and 5-qubit gates run as batched GEMMs on the matrix cores."""
     n, gates = 16, W.layered(16, 6, 11)
     want = oracle_mod.run(n, gates)
     for dtype in ("c128", "c64"):

@@ -273,6 +273,8 @@ struct MargArgs {
     int32_t sorted[24];     // marginal qubits, ascending
     uint64_t zseg;          // z values per segment
     uint32_t nseg;
+    uint32_t contig;        // every selected qubit at or above log2(zseg), zseg a multiple of 256:
+                            // a segment is one contiguous run of amplitudes
 };
 
 // deposit(z, ~S) for ascending S: insert a zero bit at every position of S.
@@ -297,10 +299,25 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const c2_t<R> *__restri
     const uint64_t xy = deposit(y, M.smask);
     double acc = 0.0;
     const uint64_t z0 = seg * M.zseg;
-    for (uint64_t z = z0 + lane; z < z0 + M.zseg; z += 64) {
-        const c2_t<R> v = a[xy | spread_out(z, M)];
-        const double re = (double)v.x, im = (double)v.y;
-        acc += re * re + im * im;
+    if (M.contig) {
+        // the segment is the run xy | spread_out(z0) + [0, zseg): each lane
+        // takes two neighbouring amplitudes per step, two steps in flight
+        const c2_t<R> *p = a + (xy | spread_out(z0, M));
+        double acc1 = 0.0;
+        for (uint64_t i = 2 * lane; i < M.zseg; i += 256) {
+            const c2_t<R> u0 = p[i], u1 = p[i + 1], u2 = p[i + 128], u3 = p[i + 129];
+            acc += (double)u0.x * (double)u0.x + (double)u0.y * (double)u0.y;
+            acc += (double)u1.x * (double)u1.x + (double)u1.y * (double)u1.y;
+            acc1 += (double)u2.x * (double)u2.x + (double)u2.y * (double)u2.y;
+            acc1 += (double)u3.x * (double)u3.x + (double)u3.y * (double)u3.y;
+        }
+        acc += acc1;
+    } else {
+        for (uint64_t z = z0 + lane; z < z0 + M.zseg; z += 64) {
+            const c2_t<R> v = a[xy | spread_out(z, M)];
+            const double re = (double)v.x, im = (double)v.y;
+            acc += re * re + im * im;
+        }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -609,6 +626,7 @@ hipError_t launch_marginal(const void *state, int n, const int *q, int nq, doubl
         k_marg_partial_lanes<R><<<blocks_for(waves * 64, kBlock), kBlock, 0, s>>>((const c2_t<R> *)state, L, scratch);
     } else {
         marg_shape(n, nq, &M.zseg, &M.nseg);
+        M.contig = (nq == 0 || (1ull << q[0]) >= M.zseg) && M.zseg % 256 == 0 ? 1u : 0u;
         nseg = M.nseg;
         const uint64_t waves = nbins * M.nseg;
         if (waves * 64 > kMaxBlocks * kBlock) return hipErrorInvalidValue;  // one wave per unit, no grid stride

@@ -458,6 +458,25 @@ def test_batch_rejects_duplicates_and_mixed_dtypes():
         s.close()
 
 
+def test_stage_at_the_phase_cap(oracle_mod):
+    """Stages of 96 register phases (a deep brickwork with every qubit
+    local) against the oracle, both dtypes."""
+    rng = np.random.default_rng(5)
+    n = 12
+    gates = []
+    for layer in range(150):
+        for a in range(layer % 2, n - 1, 2):
+            gates.append(Gate("U", (a, a + 1), 0.0, W.haar_unitary(rng, 4)))
+    want = oracle_mod.run(n, gates)
+    for dtype in ("c128", "c64"):
+        say(f"phase cap {dtype}")
+        got, _ = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_STAGES | qsim.OPT_FUSE)
+        if dtype == "c128":
+            check128(got, want, "phase cap")
+        else:
+            check64(got, want, oracle_mod, "phase cap c64")
+
+
 def test_ghz_30q_closed_form():
     """GHZ at 30 qubits: exactly two amplitudes of 1/sqrt(2)."""
     n = 30

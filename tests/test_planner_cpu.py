@@ -503,3 +503,27 @@ def test_offload_window_size_and_empty_circuit():
     # the largest window whose two copies fit the device bytes, at most n - 1
     assert qsim.Plan(n, [], opt=qsim.OPT_ALL, offload_window=15).stats()["window_qubits"] == 15
     assert qsim.Plan(n, [], opt=qsim.OPT_ALL, offload_window=16).stats()["window_qubits"] == 15
+
+
+def brickwork(n, layers, seed):
+    """Two-qubit Haar unitaries on neighbouring pairs, alternating offsets."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for layer in range(layers):
+        for a in range(layer % 2, n - 1, 2):
+            gates.append(Gate("U", (a, a + 1), 0.0, W.haar_unitary(rng, 4)))
+    return gates
+
+
+@pytest.mark.parametrize("n", [11, 12])
+def test_phase_cap_splits_the_stage(oracle_mod, n):
+    """Every qubit local and a deep brickwork: a stage reaches the cap of 96
+    register phases and the rest of the circuit moves to the next stage; the
+    plan reproduces the oracle."""
+    gates = brickwork(n, 150, 5)
+    ops, got_k, got_g = plan_state(n, gates, opt=qsim.OPT_STAGES | qsim.OPT_FUSE)
+    phases = [o["n_phases"] for o in ops if o["kind"] == "STAGE"]
+    assert phases[:3] == [96, 96, 96] and len(phases) == 4
+    want = oracle_mod.run(n, gates)
+    assert np.max(np.abs(got_k - want)) < 1e-12
+    assert np.max(np.abs(got_g - want)) < 1e-12

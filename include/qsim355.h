@@ -144,7 +144,9 @@ typedef struct {
 /* Create a context for an n_qubits state of the given dtype (the N-qubit
  * state of Sec. 2.1: 2^N complex amplitudes, qubit j = bit j of the index).
  * opts->dev_state must hold 2^n amplitudes (SIM_E_NOMEM otherwise).
- * n_qubits: 1..34.  *out receives the context (caller frees with sim_destroy). */
+ * n_qubits: 1..36 (35 qubits in complex64 fill 256 GiB of HBM; larger
+ * states need host-memory offload).  *out receives the context (caller
+ * frees with sim_destroy). */
 sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opts, sim_ctx **out);
 
 /* Validate and deep-copy the circuit (gates as defined in Sec. 2.2), then

@@ -866,7 +866,7 @@ sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opt
 {
     if (!out || !opts) return SIM_E_INVAL;
     *out = nullptr;
-    if (n_qubits < 1 || n_qubits > 34) return SIM_E_INVAL;
+    if (n_qubits < 1 || n_qubits > 36) return SIM_E_INVAL;
     if (dtype != SIM_C128 && dtype != SIM_C64) return SIM_E_INVAL;
     if (!opts->dev_state) return SIM_E_INVAL;
     const uint64_t need = (dtype == SIM_C128 ? 16ull : 8ull) << n_qubits;
@@ -1489,7 +1489,7 @@ sim_status sim_plan_build(uint32_t n_qubits, sim_dtype dtype, const sim_options 
 {
     if (!out) return SIM_E_INVAL;
     *out = nullptr;
-    if (n_qubits < 1 || n_qubits > 34 || (dtype != SIM_C128 && dtype != SIM_C64)) return SIM_E_INVAL;
+    if (n_qubits < 1 || n_qubits > 36 || (dtype != SIM_C128 && dtype != SIM_C64)) return SIM_E_INVAL;
     if (!gates && n_gates) return SIM_E_INVAL;
     std::vector<qs::Operator> ops;
     std::string err;

@@ -42,7 +42,8 @@ def test_create_validates_arguments_without_device():
     assert lib.sim_create(10, 0, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_NOMEM
     o.dev_state_bytes = 16 * 1024
     assert lib.sim_create(0, 0, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL
-    assert lib.sim_create(35, 0, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL
+    assert lib.sim_create(37, 0, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL
+    assert lib.sim_create(35, 1, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_NOMEM  # 256 GiB needed
     assert lib.sim_create(10, 7, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL
     assert lib.sim_run(None) == qsim.E_INVAL
     assert lib.sim_destroy(None) == qsim.E_INVAL

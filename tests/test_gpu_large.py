@@ -1,5 +1,6 @@
 """States of more than 2^32 amplitudes on one GPU: 33 qubits in complex128
-(128 GiB) and 34 qubits in complex64 (128 GiB), through the C ABI.
+(128 GiB), 34 qubits in complex64 (128 GiB) and complex128 (256 GiB), and 35
+qubits in complex64 (256 GiB), through the C ABI.
 
 Expected values come from closed forms evaluated per sampled index:
 
@@ -196,4 +197,26 @@ def test_34q_complex128_diagonal_closed_form():
     sim.run()
     assert np.max(np.abs(sim.amplitudes(idx) - CF.hadamard_diagonal_amplitudes(n, gates, idx))) <= TOL128
     np.testing.assert_allclose(sim.expect_z([0, 1 << 33]), [1, 0], atol=1e-12)
+    release(sim)
+
+
+def test_35q_complex64_diagonal_closed_form():
+    """The largest resident state: 35 qubits in complex64 (256 GiB). H on
+    every qubit and the fully-connected RZZ layer against the diagonal closed
+    form on sampled indices, then marginals and Z strings over the top qubit."""
+    from oracle import closed_forms as CF
+    n = 35
+    need_free(8 << n, margin=3 << 30)
+    gates = W.rzz_full(n, 7)
+    idx = W.sample_indices(n, 1 << 14, 36)
+    say(f"35q complex64 fully-connected RZZ: {len(gates)} gates")
+    sim = qsim.Simulator(n, dtype="c64", opt=qsim.OPT_ALL)
+    sim.load(gates)
+    sim.run()
+    want = CF.hadamard_diagonal_amplitudes(n, gates, idx)
+    got = sim.amplitudes(idx)
+    assert np.max(np.abs(got - want)) <= 2e-5 * np.max(np.abs(want))
+    assert abs(sim.norm() - 1) < 1e-5
+    np.testing.assert_allclose(sim.probabilities([34, 0]), [0.25] * 4, atol=1e-6)
+    np.testing.assert_allclose(sim.expect_z([0, 1 << 34, (1 << 34) | (1 << 31)]), [1, 0, 0], atol=1e-6)
     release(sim)

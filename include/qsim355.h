@@ -122,7 +122,7 @@ typedef struct {
     uint64_t n_gates;          /* gates of the loaded circuit */
     uint64_t n_ops;            /* ops of the executed plan */
     uint64_t full_passes;      /* read+write passes over the full state */
-    uint64_t write_passes;     /* write-only passes (init, tensor product) */
+    uint64_t write_passes;     /* write-only passes (init, tensor product not formed on load) */
     uint64_t read_passes;      /* read-only passes (reductions) of the last output call */
     uint64_t n_stages;         /* cache-blocked stage ops */
     uint64_t n_dense;          /* full-pass dense ops */
@@ -132,7 +132,9 @@ typedef struct {
     uint64_t n_subruns;        /* ops run on booster sub-states */
     double plan_ms;            /* host optimiser time of the last sim_load_circuit */
     double run_ms;             /* device time of the last sim_run (HIP events) */
-    double algorithmic_bytes;  /* bytes the plan moves over the full state */
+    double algorithmic_bytes;  /* bytes the plan moves over the full state (a tensor product
+                                  formed by the next stage's chunk loads counts neither its
+                                  write nor that stage's read) */
     double flops;              /* floating-point operations of the plan (estimate) */
     double est_ms;             /* device time of the plan predicted by the optimiser's cost model */
     uint64_t offload_passes;   /* host-memory offload: passes that stream the whole state through

@@ -37,6 +37,9 @@ struct Prepared {
     bool mfma = false;          // DENSE on the matrix cores (table holds the real-ified matrix)
     uint32_t item = 0;          // index of its SmallItem
     uint32_t batch = 0;         // ops of the batch starting here (0 = inside a batch)
+    bool fused = false;         // KRON formed by the next stage's chunk loads (not launched)
+    bool kron = false;          // STAGE: its chunks are the tensor product of buffers klo, khi
+    int klo = 0, khi = 0;
 };
 
 struct DevBuf {
@@ -543,6 +546,19 @@ sim_status prepare(sim_ctx *c)
         c->prep[i].batch = (uint32_t)(j - i);
         i = j;
     }
+    // the booster's last tensor product (into the full state) is formed by the
+    // next stage while it loads its chunks: the product is never written to
+    // HBM and read back
+    for (size_t i = 0; i + 1 < c->prep.size(); ++i) {
+        Prepared &k = c->prep[i], &st = c->prep[i + 1];
+        if (k.kind == SIM_OP_KRON && k.buffer == 0 && st.kind == SIM_OP_STAGE && st.buffer == 0 && !st.small &&
+            !c->window) {
+            k.fused = true;
+            st.kron = true;
+            st.klo = k.lo;
+            st.khi = k.hi;
+        }
+    }
     // upload
     const size_t amp = c->amp_bytes();
     HIPCHK(c, grow(c->tables, std::max<size_t>(tables.size() * amp, 256)), "table allocation");
@@ -679,6 +695,7 @@ hipError_t launch_op(sim_ctx *c, size_t i, hipStream_t st)
     case SIM_OP_INIT:
         return qs::launch_init<R>(c->buf(p.buffer), p.nb, st);
     case SIM_OP_KRON: {
+        if (p.fused) return hipSuccess;  // formed by the next stage's loads
         const int nlo = c->plan.buffer_qubits[p.lo], nhi = c->plan.buffer_qubits[p.hi];
         return qs::launch_kron<R>(c->buf(p.buffer), c->buf(p.lo), nlo, c->buf(p.hi), nhi, st);
     }
@@ -707,6 +724,11 @@ hipError_t launch_op(sim_ctx *c, size_t i, hipStream_t st)
             L.C = p.C;
             L.nphases = p.nph;
             L.nchunks = p.nchunks;
+            if (p.kron) {
+                L.kron_lo = c->buf(p.klo);
+                L.kron_hi = c->buf(p.khi);
+                L.kron_nlo = c->plan.buffer_qubits[p.klo];
+            }
             return qs::launch_stage<R>(L, st);
         }
     default:
@@ -772,6 +794,9 @@ sim_status execute_staged_batch(sim_ctx *const *cs, uint32_t n, hipStream_t st)
                 J.job[J.n].state = c->buf(0);
                 J.job[J.n].prog = (const uint32_t *)c->prog.p + p.prog_off;
                 J.job[J.n].tables = c->tables.p;
+                J.job[J.n].kron_lo = p.kron ? c->buf(p.klo) : nullptr;
+                J.job[J.n].kron_hi = p.kron ? c->buf(p.khi) : nullptr;
+                J.job[J.n].kron_nlo = p.kron ? c->plan.buffer_qubits[p.klo] : 0;
                 blocks += p.nchunks;
                 ++J.n;
                 ++w;
@@ -954,6 +979,12 @@ sim_status sim_load_circuit(sim_ctx *c, const sim_gate *gates, uint64_t n_gates)
     c->loaded = true;
     c->ran = false;
     fill_stats(c->plan, c->gates.size(), &c->stats);
+    // a tensor product formed on load skips one write and one read of the state
+    for (const Prepared &p : c->prep)
+        if (p.fused) {
+            c->stats.algorithmic_bytes -= 2.0 * (double)(c->amp_bytes() << c->n);
+            c->stats.write_passes -= 1;
+        }
     return SIM_OK;
 }
 
@@ -1392,6 +1423,10 @@ sim_status sim_op_timings(sim_ctx *c, sim_op_timing *out, uint64_t cap, uint64_t
         out[i].buffer = (uint32_t)c->plan.ops[i].buffer;
         out[i].flops = c->plan.ops[i].flops;
         out[i].bytes = c->plan.ops[i].bytes;
+        // a tensor product formed by the next stage's loads: no bytes of its
+        // own, and that stage reads the two factors instead of the state
+        if (c->prep[i].fused) out[i].bytes = 0;
+        if (c->prep[i].kron) out[i].bytes -= (double)(c->amp_bytes() << c->prep[i].nb);
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->op_ev[2 * i], c->op_ev[2 * i + 1]), "event time");
         out[i].ms = ms;

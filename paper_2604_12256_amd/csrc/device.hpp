@@ -159,6 +159,10 @@ struct StageLaunch {
     uint64_t nchunks;
     uint64_t xbits = 0;      // bits OR-ed into the wave-uniform base for selectors only (the
                              // outer qubits of a host-memory offload window, at bits >= n)
+    // tensor product formed on load: when kron_lo is set, the chunk is read as
+    // kron_lo[x mod 2^kron_nlo] * kron_hi[x >> kron_nlo] instead of state[x]
+    const void *kron_lo = nullptr, *kron_hi = nullptr;
+    int kron_nlo = 0;
 };
 template <typename R> hipError_t launch_stage(const StageLaunch &L, hipStream_t s);
 
@@ -171,6 +175,8 @@ struct StageJob {
     void *state;
     const uint32_t *prog;
     const void *tables;
+    const void *kron_lo, *kron_hi;  // as in StageLaunch (kron_lo NULL: read the state)
+    int32_t kron_nlo, pad;
 };
 struct StageJobs {
     uint32_t n;

@@ -308,10 +308,14 @@ __device__ __forceinline__ void transpose(c2_t<R> *amp, uint32_t lds_base, uint3
 }
 
 // The chunks first, first + step, ... below nchunks of one stage program.
+// With klo set, the chunk is the tensor product klo (x) khi formed on load
+// (Alg. 7's merge of the booster's two halves, without writing and re-reading
+// the product): amplitude x = klo[x mod 2^knlo] * khi[x >> knlo].
 template <typename R, int RB>
 __device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const uint32_t *__restrict__ Pg,
                                              const c2_t<R> *__restrict__ tables, uint64_t first, uint64_t nchunks,
-                                             uint64_t step, uint64_t xbits)
+                                             uint64_t step, uint64_t xbits, const c2_t<R> *__restrict__ klo,
+                                             const c2_t<R> *__restrict__ khi, int knlo)
 {
     using V = c2_t<R>;
     const QS_CONST uint32_t *P = as_const(Pg);
@@ -353,8 +357,17 @@ __device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const 
         // chunk bits, thread bits and register bits are disjoint: each
         // amplitude is a per-thread pointer plus a wave-uniform offset
         V *const pt = state + (cbase | tphys);
+        if (klo) {
+            const uint64_t lomask = (1ull << knlo) - 1;
 #pragma unroll
-        for (int j = 0; j < NR; ++j) amp[j] = pt[reg_phys_offset<RB>(j, regphys)];
+            for (int j = 0; j < NR; ++j) {
+                const uint64_t x = cbase | tphys | reg_phys_offset<RB>(j, regphys);
+                amp[j] = cmul(klo[x & lomask], khi[x >> knlo]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) amp[j] = pt[reg_phys_offset<RB>(j, regphys)];
+        }
         // current mapping: register mask and thread-map words (workgroup-uniform)
         uint32_t cur_lb = tid, cur_r = neutral_r;
         uint32_t cur_t0 = neutral_t[0], cur_t1 = neutral_t[1], cur_t2 = neutral_t[2];
@@ -432,9 +445,11 @@ template <typename R, int RB>
 __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
                                                             const uint32_t *__restrict__ Pg,
                                                             const c2_t<R> *__restrict__ tables,
-                                                            uint64_t nchunks, uint64_t xbits)
+                                                            uint64_t nchunks, uint64_t xbits,
+                                                            const c2_t<R> *__restrict__ klo,
+                                                            const c2_t<R> *__restrict__ khi, int knlo)
 {
-    stage_chunks<R, RB>(state, Pg, tables, blockIdx.x, nchunks, gridDim.x, xbits);
+    stage_chunks<R, RB>(state, Pg, tables, blockIdx.x, nchunks, gridDim.x, xbits, klo, khi, knlo);
 }
 
 // Stages of several independent states (one stage program each, same chunk
@@ -452,7 +467,8 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage_multi(const StageJob
     }
     const StageJob &job = J.job[lo];
     const uint64_t chunk = b - J.first_block[lo];
-    stage_chunks<R, RB>((c2_t<R> *)job.state, job.prog, (const c2_t<R> *)job.tables, chunk, chunk + 1, 1, 0);
+    stage_chunks<R, RB>((c2_t<R> *)job.state, job.prog, (const c2_t<R> *)job.tables, chunk, chunk + 1, 1, 0,
+                        (const c2_t<R> *)job.kron_lo, (const c2_t<R> *)job.kron_hi, job.kron_nlo);
 }
 
 }  // namespace
@@ -479,8 +495,10 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     // against fewer, longer-lived workgroups)
     uint64_t grid = L.nchunks;
     if (grid > (1ull << 15)) grid = 1ull << 15;
+    if (L.kron_lo && (L.kron_nlo < 1 || L.kron_nlo >= L.n || !L.kron_hi)) return hipErrorInvalidValue;
     k_stage<R, RB><<<(uint32_t)grid, threads, lds, s>>>((c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables,
-                                                        L.nchunks, L.xbits);
+                                                        L.nchunks, L.xbits, (const c2_t<R> *)L.kron_lo,
+                                                        (const c2_t<R> *)L.kron_hi, L.kron_nlo);
     return hipGetLastError();
 }
 

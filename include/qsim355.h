@@ -87,7 +87,9 @@ enum {
 
 typedef struct {
     uint32_t opt;          /* SIM_OPT_* flags; 0 = gate by gate (Alg. 1) */
-    uint32_t C;            /* chunk qubits of a stage (0 = default for the dtype) */
+    uint32_t C;            /* chunk qubits of a stage: 0 = default (12 for C128, 13 for C64);
+                              otherwise 10..13 (C128) or 11..14 (C64), else sim_create
+                              returns SIM_E_INVAL */
     uint32_t F;            /* max qubits of a fused dense gate (0 = default 5) */
     uint32_t D;            /* max qubits of a fused diagonal (0 = default 10) */
     uint32_t B;            /* booster division parameter (0 = default 4) */

@@ -894,6 +894,10 @@ sim_status sim_create(uint32_t n_qubits, sim_dtype dtype, const sim_options *opt
     if (n_qubits < 1 || n_qubits > 36) return SIM_E_INVAL;
     if (dtype != SIM_C128 && dtype != SIM_C64) return SIM_E_INVAL;
     if (!opts->dev_state) return SIM_E_INVAL;
+    // a stage chunk spans at least one full wave of register tiles (2^(rb+6))
+    // and at most one 512-thread workgroup of them (2^(rb+9))
+    const uint32_t rb = dtype == SIM_C128 ? 4u : 5u;
+    if (opts->C && (opts->C < rb + 6 || opts->C > rb + 9)) return SIM_E_INVAL;
     const uint64_t need = (dtype == SIM_C128 ? 16ull : 8ull) << n_qubits;
     if (opts->host_state) {
         // host-memory offload: the state is in host memory, the device

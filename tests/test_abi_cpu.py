@@ -45,6 +45,11 @@ def test_create_validates_arguments_without_device():
     assert lib.sim_create(37, 0, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL
     assert lib.sim_create(35, 1, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_NOMEM  # 256 GiB needed
     assert lib.sim_create(10, 7, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL
+    # stage chunks: 10..13 qubits in complex128, 11..14 in complex64
+    for dtype, C in ((0, 9), (0, 14), (1, 10), (1, 15)):
+        o.C = C
+        assert lib.sim_create(10, dtype, ctypes.byref(o), ctypes.byref(ctx)) == qsim.E_INVAL, (dtype, C)
+    o.C = 0
     assert lib.sim_run(None) == qsim.E_INVAL
     assert lib.sim_destroy(None) == qsim.E_INVAL
     assert lib.sim_last_error(None) == b"null context"

@@ -1035,10 +1035,20 @@ sim_status sim_amplitudes(sim_ctx *c, const uint64_t *idx, uint64_t m, double *o
     const std::vector<int> &lay = c->layout;
     bool identity = true;
     for (int q = 0; q < c->n; ++q) identity &= (lay[q] == q);
+    // logical -> physical index, one table lookup per byte of the index
+    const int nbytes = (c->n + 7) / 8;
+    std::vector<uint64_t> spread(identity ? 0 : (size_t)nbytes * 256);
+    for (int b = 0; b < (int)spread.size() / 256; ++b)
+        for (uint32_t v = 0; v < 256; ++v) {
+            uint64_t y = 0;
+            for (int t = 0; t < 8 && 8 * b + t < c->n; ++t)
+                if ((v >> t) & 1) y |= 1ull << lay[8 * b + t];
+            spread[256 * b + v] = y;
+        }
     auto phys = [&](uint64_t x) {
         if (identity) return x;
         uint64_t y = 0;
-        for (int q = 0; q < c->n; ++q) y |= ((x >> q) & 1ull) << lay[q];
+        for (int b = 0; b < nbytes; ++b) y |= spread[256 * b + ((x >> (8 * b)) & 255)];
         return y;
     };
     HIPCHK(c, hipStreamSynchronize(c->stream), "synchronize");

@@ -2,10 +2,14 @@
 oracle (and nothing else) on the seeded workload circuits.
 
     python tests/golden/make_golden.py layered28 layered30 diag30
+    python tests/golden/make_golden.py --sketch layered28 layered30 diag30
 
 Each output file holds, for one circuit: the oracle's norm, two marginal
-distributions and the amplitudes at seeded sample indices.  Values are
-printed with 17 significant digits (exact binary64 round trip).
+distributions and the amplitudes at seeded sample indices.  With --sketch
+the file <name>_sketch.txt holds instead the seeded projections of the
+whole state (tests/golden/sketch.py), after checking that the recomputed
+state still reproduces the stored sample amplitudes bit for bit.  Values
+are printed with 17 significant digits (exact binary64 round trip).
 """
 import os
 import sys
@@ -18,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 from oracle import oracle  # noqa: E402
 from paper_2604_12256_amd import workloads as W  # noqa: E402
+from tests.golden.sketch import N_PROJ, sketch  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 N_SAMPLES = 4096
@@ -52,6 +57,42 @@ def write(name: str) -> None:
     del state
 
 
+def write_sketch(name: str) -> None:
+    n, gates = W.config_circuit(name)
+    t0 = time.time()
+    state = oracle.run(n, gates)
+    dt = time.time() - t0
+    stored = read(name)
+    same = np.array_equal(state[stored["idx"].astype(np.int64)], stored["amp"])
+    if not same:
+        raise SystemExit(f"{name}: the recomputed oracle state differs from the stored samples")
+    s = sketch(state)
+    path = os.path.join(HERE, f"{name}_sketch.txt")
+    with open(path, "w") as f:
+        f.write(f"# oracle output for workload {name}: n={n} gates={len(gates)}\n")
+        f.write(f"# written by tests/golden/make_golden.py --sketch (CPU oracle only), {oracle.num_threads()} "
+                f"threads, {dt:.0f} s; the state reproduces the stored samples of {name}.txt bit for bit\n")
+        f.write(f"# {N_PROJ} projections s_k = sum_x w_k(x) a_x of tests/golden/sketch.py\n")
+        for k, v in enumerate(s):
+            f.write(f"sketch {k} {v.real:.17g} {v.imag:.17g}\n")
+    print(f"{name}: n={n} gates={len(gates)} oracle {dt:.1f} s -> {path}", flush=True)
+    del state
+
+
+def read_sketch(name: str):
+    """The stored projections of <name>_sketch.txt, or None when absent."""
+    path = os.path.join(HERE, f"{name}_sketch.txt")
+    if not os.path.exists(path):
+        return None
+    vals = []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("sketch"):
+                parts = line.split()
+                vals.append(complex(float(parts[2]), float(parts[3])))
+    return np.array(vals, dtype=np.complex128)
+
+
 def read(name: str):
     """Parse a golden file: dict(norm, marginals {tuple(qubits): array}, idx, amp)."""
     path = os.path.join(HERE, f"{name}.txt")
@@ -78,5 +119,9 @@ def read(name: str):
 
 if __name__ == "__main__":
     oracle.build(force=False)
-    for name in sys.argv[1:]:
-        write(name)
+    names = [a for a in sys.argv[1:] if not a.startswith("--")]
+    for name in names:
+        if "--sketch" in sys.argv:
+            write_sketch(name)
+        else:
+            write(name)

@@ -262,7 +262,12 @@ def golden(name):
 @pytest.mark.parametrize("name", ["layered28", "layered30", "diag30"])
 def test_full_size_against_golden(name):
     """Full-size workloads in the benchmark's configuration (all passes on),
-    on the oracle's stored sample amplitudes, marginals and norm."""
+    on the oracle's stored sample amplitudes, marginals and norm, and on the
+    whole state through its seeded projections: a wrong amplitude anywhere
+    moves every projection by its error (bound 1e-10; rounding differences
+    spread over the state move them by about 1e-13)."""
+    from tests.golden.make_golden import read_sketch
+    from tests.golden.sketch import sketch
     g = golden(name)
     n, gates = W.config_circuit(name)
     say(f"full size {name}")
@@ -274,6 +279,11 @@ def test_full_size_against_golden(name):
     assert abs(sim.norm() - g["norm"]) < 1e-12
     for qs, ref in g["marginals"].items():
         assert np.max(np.abs(sim.probabilities(list(qs)) - ref)) < 1e-12
+    s_ref = read_sketch(name)
+    if s_ref is not None:
+        say(f"full size {name}: whole-state projections")
+        err = np.max(np.abs(sketch(sim.amplitudes()) - s_ref))
+        assert err < 1e-10, f"{name}: projections differ by {err:.3e}"
     sim.close()
 
 

@@ -82,7 +82,12 @@ enum {
     SIM_OPT_REMAP = 1u << 4,   /* qubit reordering (Sec. 2.3): permutation passes between
                                   stages (needs STAGES), and SWAP gates (an exact 0/1 exchange
                                   matrix) become relabellings that move no data */
-    SIM_OPT_ALL = 0x1Fu
+    SIM_OPT_QUAD = 1u << 5,    /* with FUSE: the one- and two-qubit diagonals a register phase
+                                  collects become one quadratic-phase operator (phase
+                                  c + sum a_q x_q + sum b_qp x_q x_p) when that costs less than
+                                  their diagonal tables; complex128 only, not used with
+                                  host-memory offload */
+    SIM_OPT_ALL = 0x3Fu
 };
 
 typedef struct {

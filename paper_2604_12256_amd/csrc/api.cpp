@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -40,6 +41,7 @@ struct Prepared {
     bool fused = false;         // KRON formed by the next stage's chunk loads (not launched)
     bool kron = false;          // STAGE: its chunks are the tensor product of buffers klo, khi
     int klo = 0, khi = 0;
+    bool quad = false;          // STAGE: has quadratic-phase operators (kernel variant with them)
 };
 
 struct DevBuf {
@@ -186,6 +188,91 @@ bool convert_gates(const sim_gate *gates, uint64_t ng, int n, std::vector<qs::Op
     return true;
 }
 
+// Device form of a quadratic-phase operator in one register phase (the
+// kernel side is quad_op in kernel_stage.hip): one block of complex FP64 unit
+// factors (appended to `block`; the caller stores it in the program words, so
+// that it keeps FP64 for complex64 states too).  First the per-thread rows, indexed by the thread id:
+// e^{i(c + form on the thread bits)}, then for each register bit b
+// e^{i(a_b + sum over set thread bits t of b(t, b))}; then e^{i b(b, b')} for
+// the register-bit pairs b < b'.  Then the chunk rows: the chunk bits are the
+// buffer's global qubits in ascending order, and the chunk index g splits
+// into its low h bits and the rest.  Low row g_lo: e^{i beta_j(g_lo)} for the
+// C local bits j, e^{i gamma_l(g_lo)} for the high chunk bits hi_l (gamma_l =
+// sum over set low bits i of b(i, hi_l)), then e^{i phi(g_lo)}; high row g_hi:
+// e^{i beta_j(g_hi)} for j < C, then e^{i phi(g_hi)}, with beta_j(g) the sum
+// over set chunk bits i of b(i, j) and phi(g) the form on the chunk bits
+// alone.  A row is the row of g without its top bit times that bit's factors
+// (one complex multiply per entry); the phase column is summed as an angle.
+// Returns the entry offsets of the low and the high rows in the block,
+// h | (number of high bits) << 8, and the entry offset of the pair factors.
+static std::array<uint32_t, 4> encode_quad(const qs::KOp &k, int C, int n, int reg_bits, uint32_t rmask,
+                                                 const std::vector<int> &tmap, const std::vector<int> &local,
+                                                 uint64_t L, std::vector<cplx> &tables)
+{
+    auto B = [&](int q, int p) { return q < p ? k.qb[(size_t)q * n + p] : k.qb[(size_t)p * n + q]; };
+    const size_t start = tables.size();
+    // register bit b <-> the b-th set bit of the register mask (local index)
+    int regloc[8], nr = 0;
+    for (int i = 0; i < C; ++i)
+        if ((rmask >> i) & 1) regloc[nr++] = i;
+    if (nr != reg_bits) throw std::runtime_error("encode_quad: register mask");
+    const int nt = C - reg_bits;
+    for (uint64_t tid = 0; tid < (1ull << nt); ++tid) {
+        double e = k.qc;
+        for (int i = 0; i < nt; ++i) {
+            if (!((tid >> i) & 1)) continue;
+            const int qi = local[tmap[i]];
+            e += k.qa[qi];
+            for (int i2 = i + 1; i2 < nt; ++i2)
+                if ((tid >> i2) & 1) e += B(qi, local[tmap[i2]]);
+        }
+        tables.push_back(std::polar(1.0, e));
+        for (int b = 0; b < reg_bits; ++b) {
+            const int qb = local[regloc[b]];
+            double u = k.qa[qb];
+            for (int i = 0; i < nt; ++i)
+                if ((tid >> i) & 1) u += B(local[tmap[i]], qb);
+            tables.push_back(std::polar(1.0, u));
+        }
+    }
+    const uint32_t pairs = (uint32_t)(tables.size() - start);
+    for (int b = 0; b < reg_bits; ++b)
+        for (int b2 = b + 1; b2 < reg_bits; ++b2)
+            tables.push_back(std::polar(1.0, B(local[regloc[b]], local[regloc[b2]])));
+    std::vector<int> gpos;
+    for (int q = 0; q < n; ++q)
+        if (!((L >> q) & 1)) gpos.push_back(q);
+    const int nG = (int)gpos.size(), h = (nG + 1) / 2, nhi = nG - h;
+    auto rows = [&](int first, int nb, bool cross) {
+        const int ncol = C + (cross ? nhi : 0) + 1;
+        const size_t at = tables.size();
+        tables.resize(at + ((size_t)ncol << nb), cplx(1.0, 0.0));
+        std::vector<double> phi((size_t)1 << nb, 0.0);
+        std::vector<cplx> f(ncol - 1);
+        for (int t = 0; t < nb; ++t) {
+            const int qt = gpos[first + t];
+            for (int j = 0; j < C; ++j) f[j] = std::polar(1.0, B(qt, local[j]));
+            if (cross)
+                for (int l = 0; l < nhi; ++l) f[C + l] = std::polar(1.0, B(qt, gpos[h + l]));
+            for (uint64_t g = 1ull << t; g < (2ull << t); ++g) {
+                const uint64_t g0 = g ^ (1ull << t);
+                cplx *row = &tables[at + g * ncol];
+                const cplx *prev = &tables[at + g0 * ncol];
+                for (int c = 0; c < ncol - 1; ++c) row[c] = prev[c] * f[c];
+                double d = k.qa[qt];
+                for (int i = 0; i < t; ++i)
+                    if ((g0 >> i) & 1) d += B(gpos[first + i], qt);
+                phi[g] = phi[g0] + d;
+            }
+        }
+        for (uint64_t g = 0; g < (1ull << nb); ++g) tables[at + g * ncol + ncol - 1] = std::polar(1.0, phi[g]);
+        return (uint32_t)(at - start);
+    };
+    const uint32_t lo = rows(0, h, true);
+    const uint32_t hi = rows(h, nhi, false);
+    return {lo, hi, (uint32_t)h | ((uint32_t)nhi << 8), pairs};
+}
+
 // Program words of one stage (layout documented in kernel_stage.hip).
 // amp_bytes: bytes of one table entry on the device (16 complex128, 8 complex64).
 void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::vector<uint32_t> &w,
@@ -232,6 +319,8 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
         const uint32_t neutral_r = ((1u << C) - 1) & ~((1u << (C - reg_bits)) - 1);
         reg_offsets(neutral_r, &w[base + 128]);
     }
+    std::vector<uint32_t> qwords;                    // FP64 blocks of quadratic-phase operators
+    std::vector<std::pair<size_t, size_t>> qpatch;  // (op word in w, block offset in qwords)
     for (size_t p = 0; p < st.phases.size(); ++p) {
         const qs::Phase &ph = st.phases[p];
         w[base + 32 + p] = (uint32_t)(w.size() - base);
@@ -261,6 +350,21 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
             const qs::KOp &k = ph.ops[o];
             uint32_t *op = &w[pb + qs::kStagePhaseWords + NR + 16 * o];
             const uint64_t toff = tables.size();
+            if (k.type == qs::KOp::QUAD) {
+                std::vector<cplx> blk;
+                const auto offs = encode_quad(k, C, n, reg_bits, rmask, ph.tmap, st.local, L, blk);
+                op[0] = 3u;
+                op[4] = offs[0];
+                op[5] = offs[2];
+                op[6] = offs[1];
+                op[7] = offs[3];
+                // word offset of the block, set once the phases are laid out
+                qpatch.push_back({(size_t)(op - w.data()) + 3, qwords.size()});
+                const size_t at = qwords.size();
+                qwords.resize(at + 4 * blk.size());
+                std::memcpy(&qwords[at], blk.data(), blk.size() * sizeof(cplx));
+                continue;
+            }
             uint32_t mask = 0;
             std::vector<int> sel;
             if (k.type == qs::KOp::DENSE) {
@@ -373,6 +477,14 @@ void encode_stage(const qs::PlanOp &st, int reg_bits, uint32_t amp_bytes, std::v
             op[1] = (uint32_t)tbytes;
             op[2] = (uint32_t)(tbytes >> 32);
         }
+    }
+    if (!qwords.empty()) {
+        // the FP64 blocks follow the phases, 16-byte aligned in the program
+        // buffer (its device copy starts at a 256-byte boundary)
+        while (w.size() & 3) w.push_back(0);
+        const size_t at = w.size();
+        w.insert(w.end(), qwords.begin(), qwords.end());
+        for (const auto &pq : qpatch) w[pq.first] = (uint32_t)(at + pq.second - base);
     }
 }
 
@@ -505,6 +617,8 @@ sim_status prepare(sim_ctx *c)
                 p.nph = (int)op.phases.size();
                 p.nchunks = 1ull << (op.buffer_qubits - p.C);
                 encode_stage(op, c->opt.reg_bits, c->dtype == SIM_C64 ? 8u : 16u, prog, tables);
+                for (const qs::Phase &ph : op.phases)
+                    for (const qs::KOp &k : ph.ops) p.quad |= k.type == qs::KOp::QUAD;
             }
             break;
         }
@@ -616,6 +730,7 @@ hipError_t launch_window_op(sim_ctx *c, const Prepared &p, void *buf, uint64_t x
         L.nphases = p.nph;
         L.nchunks = p.nchunks;
         L.xbits = xbits;
+        L.quad = p.quad;
         return qs::launch_stage<R>(L, c->stream);
     }
     case SIM_OP_DENSE:
@@ -729,6 +844,7 @@ hipError_t launch_op(sim_ctx *c, size_t i, hipStream_t st)
                 L.kron_hi = c->buf(p.khi);
                 L.kron_nlo = c->plan.buffer_qubits[p.klo];
             }
+            L.quad = p.quad;
             return qs::launch_stage<R>(L, st);
         }
     default:
@@ -786,6 +902,7 @@ sim_status execute_staged_batch(sim_ctx *const *cs, uint32_t n, hipStream_t st)
             qs::StageJobs J{};
             size_t w = w0;
             uint64_t blocks = 0;
+            bool quad = false;
             while (w < wait.size() && J.n < qs::kStageJobsMax) {
                 sim_ctx *c = cs[wait[w]];
                 const Prepared &p = c->prep[cur[wait[w]]];
@@ -797,12 +914,13 @@ sim_status execute_staged_batch(sim_ctx *const *cs, uint32_t n, hipStream_t st)
                 J.job[J.n].kron_lo = p.kron ? c->buf(p.klo) : nullptr;
                 J.job[J.n].kron_hi = p.kron ? c->buf(p.khi) : nullptr;
                 J.job[J.n].kron_nlo = p.kron ? c->plan.buffer_qubits[p.klo] : 0;
+                quad |= p.quad;
                 blocks += p.nchunks;
                 ++J.n;
                 ++w;
             }
             J.first_block[J.n] = (uint32_t)blocks;
-            const hipError_t e = qs::launch_stage_multi<R>(J, C, st);
+            const hipError_t e = qs::launch_stage_multi<R>(J, C, quad, st);
             if (e != hipSuccess) return hip_fail(cs[wait[w0]], e, "batched stage launch");
             for (size_t u = w0; u < w; ++u) ++cur[wait[u]];
             w0 = w;
@@ -1654,6 +1772,28 @@ sim_status sim_plan_stage_kernel_op(const sim_plan *p, uint64_t op_index, uint64
         }
         const qs::KOp &k = ph.ops[i];
         std::memset(g, 0, sizeof(*g));
+        if (k.type == qs::KOp::QUAD) {
+            // (code, angle) pairs: code -1 the constant, q * 64 + q the
+            // linear term of qubit q, q * 64 + p (q < p) the pair term
+            std::vector<std::pair<double, double>> terms{{-1.0, k.qc}};
+            const int nb = o.buffer_qubits;
+            for (int q = 0; q < nb; ++q) {
+                if (k.qa[q] != 0.0) terms.push_back({(double)(wm(q) * 64 + wm(q)), k.qa[q]});
+                for (int p2 = q + 1; p2 < nb; ++p2) {
+                    const double v = k.qb[(size_t)q * nb + p2];
+                    const int a = std::min(wm(q), wm(p2)), bq = std::max(wm(q), wm(p2));
+                    if (v != 0.0) terms.push_back({(double)(a * 64 + bq), v});
+                }
+            }
+            g->diagonal = 2;
+            g->payload_len = terms.size();
+            if (payload)
+                for (size_t t = 0; t < terms.size(); ++t) {
+                    payload[2 * t] = terms[t].first;
+                    payload[2 * t + 1] = terms[t].second;
+                }
+            return SIM_OK;
+        }
         if (k.type == qs::KOp::DIAG) {
             g->diagonal = 1;
             g->nq = (uint32_t)k.dq.size();

@@ -163,6 +163,10 @@ struct StageLaunch {
     // kron_lo[x mod 2^kron_nlo] * kron_hi[x >> kron_nlo] instead of state[x]
     const void *kron_lo = nullptr, *kron_hi = nullptr;
     int kron_nlo = 0;
+    // the program holds quadratic-phase operators: launched on the kernel
+    // variant that has them (the others keep the register allocation of the
+    // kernel without)
+    bool quad = false;
 };
 template <typename R> hipError_t launch_stage(const StageLaunch &L, hipStream_t s);
 
@@ -183,7 +187,7 @@ struct StageJobs {
     uint32_t first_block[kStageJobsMax + 1];
     StageJob job[kStageJobsMax];
 };
-template <typename R> hipError_t launch_stage_multi(const StageJobs &J, int C, hipStream_t s);
+template <typename R> hipError_t launch_stage_multi(const StageJobs &J, int C, bool quad, hipStream_t s);
 
 hipError_t launch_copy(void *dst, const void *src, uint64_t bytes, hipStream_t s);
 // host-memory offload: window v (outer qubits fixed) between the mapped host

@@ -63,7 +63,7 @@ Operator gate_operator(const sim_gate &g, int n_qubits, std::string *err);
 
 // One op executed by the stage kernel on the registers of a phase.
 struct KOp {
-    enum Type : uint32_t { DENSE = 1, DIAG = 2 } type;
+    enum Type : uint32_t { DENSE = 1, DIAG = 2, QUAD = 3 } type;
     uint32_t reg_mask = 0;            // DENSE: register bits acted on
     std::vector<int> sel;             // physical qubits selecting the block (DENSE)
     std::vector<int> dq;              // DIAG: physical qubits of the table index (bit t <-> dq[t])
@@ -71,6 +71,16 @@ struct KOp {
     // DIAG built from several diagonals: the members, multiplied into `table`
     // once the plan is final (planning compares lowerings before that)
     std::vector<Operator> members;
+    // QUAD: a diagonal whose phase is a quadratic form of the index bits,
+    // phi(x) = qc + sum_q qa[q] x_q + sum_{q<p} qb[q * n + p] x_q x_p over the
+    // buffer's n physical qubits (the product of members on one or two
+    // qubits: every such diagonal of unit modulus has this form exactly)
+    double qc = 0;
+    std::vector<double> qa, qb;
+    // QUAD while planning: the diagonal tables it replaces, and their cost
+    // (microseconds per 2^30 amplitudes), in case the stage keeps tables
+    std::vector<KOp> alt;
+    double alt_us = 0;
 };
 
 struct Phase {

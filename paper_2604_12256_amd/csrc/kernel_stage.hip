@@ -25,7 +25,7 @@
 //           [8, 9] physical bit of wave bit i (bytes)
 //           [16 + j] LDS byte offset of register j (swizzled; j < 2^RB)
 //           [16 + 2^RB + 16 o ...] op o (a 64-byte record)
-//   op      [0] type (bits 0-7: 1 dense, 2 diagonal) | register mask (bits of the
+//   op      [0] type (bits 0-7: 1 dense, 2 diagonal, 3 quadratic phase) | register mask (bits of the
 //           register tile the operator acts on) << 8 | selector count << 16 (5 bits) |
 //           bit fields F << 21 (3 bits) | selectors wave-uniform << 24 |
 //           log2 of the table bytes per selector value << 25
@@ -37,6 +37,11 @@
 //           filling the selector from bit 0 up
 //   A dense op's table holds 2^nsel matrices of (2^k)^2 entries, a diagonal
 //   op's 2^nsel blocks of 2^k factors (k = popcount of the register mask).
+//   A quadratic-phase op: [3] word offset (from the program start) of its
+//   block of complex FP64 factors, [4], [6], [7] entry offsets in the block of
+//   its low chunk rows, high chunk rows and register-pair factors, [5]
+//   h | nhi << 8 (the chunk-index bits of the low and the high rows); see
+//   quad_op.  Only the kernel variant with quadratic-phase operators runs them.
 #include "device.hpp"
 
 namespace qs {
@@ -307,11 +312,85 @@ __device__ __forceinline__ void transpose(c2_t<R> *amp, uint32_t lds_base, uint3
     }
 }
 
+// Quadratic-phase operator (op type 3): amplitude x is multiplied by
+// e^{i phi(x)}, phi(x) = c + sum a_q x_q + sum b_qp x_q x_p over the buffer's
+// qubits, for complex128 stages.  Its block of complex FP64
+// unit factors (in the program words) holds, for the chunk's share, rows
+// selected by the low and the high half of the chunk index: lane l < C forms
+// B_l = e^{i beta_l} (the coefficient the chunk bits give local bit l) as the
+// product of its two row entries, and a wave product over the other lanes
+// forms the chunk bits' own factor E.  A thread starts from its table entry
+// (constant and thread-bit terms) times E, takes in B of each set thread bit,
+// and walks its 2^RB amplitudes in Gray-code order with a running product:
+// flipping register bit b multiplies by G_b = e^{i(a_b + thread and chunk
+// terms of b)} (or its conjugate) and by the pair factors with the register
+// bits already set.
+template <typename R, int RB>
+__device__ __forceinline__ void quad_op(c2_t<R> *amp, const OpRec &rec, const uint32_t *Pg, uint64_t chunk,
+                                        uint32_t tid, int C, uint32_t rmask, uint32_t t0, uint32_t t1, uint32_t t2)
+{
+    using V = c2_t<double>;
+    constexpr int NR = 1 << RB;
+    const int h = (int)(rec.w[5] & 0xffu), nhi = (int)((rec.w[5] >> 8) & 0xffu);
+    const int ncl = C + nhi + 1, nch = C + 1;
+    const int lane = (int)(tid & 63u);
+    const uint64_t glo = chunk & ((1ull << h) - 1), ghi = chunk >> h;
+    const V *blk = reinterpret_cast<const V *>(Pg + rec.w[3]);
+    const V *tlo = blk + rec.w[4] + glo * (uint64_t)ncl;
+    const V *thi = blk + rec.w[6] + ghi * (uint64_t)nch;
+    const V one{1.0, 0.0};
+    const V vlo = lane < ncl ? tlo[lane] : one;
+    const V vhi = lane < nch ? thi[lane] : one;
+    const V B = cmul(vlo, vhi);
+    V p = one;
+    if (lane >= C && lane < C + nhi && ((ghi >> (lane - C)) & 1ull)) p = vlo;
+    if (lane == C + nhi) p = vlo;
+    if (lane == C) p = cmul(p, vhi);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) p = cmul(p, V{__shfl_xor(p.x, off), __shfl_xor(p.y, off)});
+
+    const int nt = C - RB;
+    const V *row = blk + (size_t)tid * (1 + RB);
+    const V *qm = blk + rec.w[7];
+    V F = cmul(row[0], p);
+    for (int i = 0; i < nt; ++i) {
+        const uint32_t w = i < 4 ? t0 : i < 8 ? t1 : t2;
+        const int j = (int)((w >> (8 * (i & 3))) & 0xffu);
+        const V f2 = cmul(F, V{__shfl(B.x, j), __shfl(B.y, j)});
+        if ((tid >> i) & 1u) F = f2;
+    }
+    V G[RB];
+    uint32_t rm = rmask;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+        const int j = __builtin_ctz(rm);
+        rm &= rm - 1u;
+        G[b] = cmul(row[1 + b], V{__shfl(B.x, j), __shfl(B.y, j)});
+    }
+    V Q = F;
+    amp[0] = cmul(amp[0], c2_t<R>{(R)Q.x, (R)Q.y});
+#pragma unroll
+    for (int k = 1; k < NR; ++k) {
+        const int g = k ^ (k >> 1), b = __builtin_ctz(k), prev = g ^ (1 << b);
+        const bool set = (g >> b) & 1;
+        V f = set ? G[b] : V{G[b].x, -G[b].y};
+#pragma unroll
+        for (int b2 = 0; b2 < RB; ++b2) {
+            if (b2 == b || !((prev >> b2) & 1)) continue;
+            const int lo = b < b2 ? b : b2, hi = b < b2 ? b2 : b;
+            const V q = qm[lo * (2 * RB - lo - 1) / 2 + (hi - lo - 1)];
+            f = cmul(f, set ? q : V{q.x, -q.y});
+        }
+        Q = cmul(Q, f);
+        amp[g] = cmul(amp[g], c2_t<R>{(R)Q.x, (R)Q.y});
+    }
+}
+
 // The chunks first, first + step, ... below nchunks of one stage program.
 // With klo set, the chunk is the tensor product klo (x) khi formed on load
 // (Alg. 7's merge of the booster's two halves, without writing and re-reading
 // the product): amplitude x = klo[x mod 2^knlo] * khi[x >> knlo].
-template <typename R, int RB>
+template <typename R, int RB, bool QD>
 __device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const uint32_t *__restrict__ Pg,
                                              const c2_t<R> *__restrict__ tables, uint64_t first, uint64_t nchunks,
                                              uint64_t step, uint64_t xbits, const c2_t<R> *__restrict__ klo,
@@ -396,6 +475,12 @@ __device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const 
             const QS_CONST uint32_t *recs = ph + 16 + NR;
             auto apply_op = [&](const OpRec &rec, uint32_t o) __attribute__((always_inline)) {
                 const uint32_t head = rec.w[0];
+                if constexpr (QD) {
+                    if ((head & 0xffu) == 3u) {
+                        quad_op<R, RB>(amp, rec, Pg, chunk, tid, C, rmask, t0, t1, t2);
+                        return;
+                    }
+                }
                 const uint32_t mask = (head >> 8) & 0xffu, nsel = (head >> 16) & 0x1fu, shift = head >> 25;
                 const uint64_t toff = (uint64_t)rec.w[1] | ((uint64_t)rec.w[2] << 32);
                 if ((head >> 24) & 1u) {
@@ -441,7 +526,7 @@ __device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const 
     }
 }
 
-template <typename R, int RB>
+template <typename R, int RB, bool QD>
 __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict__ state,
                                                             const uint32_t *__restrict__ Pg,
                                                             const c2_t<R> *__restrict__ tables,
@@ -449,13 +534,13 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(c2_t<R> *__restrict_
                                                             const c2_t<R> *__restrict__ klo,
                                                             const c2_t<R> *__restrict__ khi, int knlo)
 {
-    stage_chunks<R, RB>(state, Pg, tables, blockIdx.x, nchunks, gridDim.x, xbits, klo, khi, knlo);
+    stage_chunks<R, RB, QD>(state, Pg, tables, blockIdx.x, nchunks, gridDim.x, xbits, klo, khi, knlo);
 }
 
 // Stages of several independent states (one stage program each, same chunk
 // size) in one launch: workgroup b runs chunk b - first_block[j] of job j,
 // where job j is the last with first_block[j] <= b.
-template <typename R, int RB>
+template <typename R, int RB, bool QD>
 __global__ __launch_bounds__(kStageMaxThreads) void k_stage_multi(const StageJobs J)
 {
     const uint32_t b = blockIdx.x;
@@ -467,8 +552,21 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage_multi(const StageJob
     }
     const StageJob &job = J.job[lo];
     const uint64_t chunk = b - J.first_block[lo];
-    stage_chunks<R, RB>((c2_t<R> *)job.state, job.prog, (const c2_t<R> *)job.tables, chunk, chunk + 1, 1, 0,
-                        (const c2_t<R> *)job.kron_lo, (const c2_t<R> *)job.kron_hi, job.kron_nlo);
+    stage_chunks<R, RB, QD>((c2_t<R> *)job.state, job.prog, (const c2_t<R> *)job.tables, chunk, chunk + 1, 1, 0,
+                            (const c2_t<R> *)job.kron_lo, (const c2_t<R> *)job.kron_hi, job.kron_nlo);
+}
+
+template <typename R, int RB, bool QD> hipError_t stage_lds_attr()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)k_stage<R, RB, QD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kStageLdsBytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_stage_multi<R, RB, QD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kStageLdsBytes);
+    done = e == hipSuccess;
+    return e;
 }
 
 }  // namespace
@@ -482,13 +580,13 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     const uint32_t threads = 1u << (C - RB);
     const uint32_t lds = (uint32_t)sizeof(c2_t<R>) << C;
     if (threads > (uint32_t)kStageMaxThreads || lds > kStageLdsBytes) return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_stage<R, RB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kStageLdsBytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // quadratic-phase operators exist for complex128 stages only
+    if constexpr (sizeof(R) != 8)
+        if (L.quad) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if constexpr (sizeof(R) == 8) e = L.quad ? stage_lds_attr<R, RB, true>() : stage_lds_attr<R, RB, false>();
+    else e = stage_lds_attr<R, RB, false>();
+    if (e != hipSuccess) return e;
     // at most 2^15 workgroups: on large states each walks several chunks, so
     // its set-up (thread bases, mapping tables) is paid once per several
     // chunks (measured best on MI355X against one chunk per workgroup and
@@ -496,14 +594,22 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     uint64_t grid = L.nchunks;
     if (grid > (1ull << 15)) grid = 1ull << 15;
     if (L.kron_lo && (L.kron_nlo < 1 || L.kron_nlo >= L.n || !L.kron_hi)) return hipErrorInvalidValue;
-    k_stage<R, RB><<<(uint32_t)grid, threads, lds, s>>>((c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables,
-                                                        L.nchunks, L.xbits, (const c2_t<R> *)L.kron_lo,
-                                                        (const c2_t<R> *)L.kron_hi, L.kron_nlo);
+    if constexpr (sizeof(R) == 8) {
+        if (L.quad) {
+            k_stage<R, RB, true><<<(uint32_t)grid, threads, lds, s>>>(
+                (c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables, L.nchunks, L.xbits,
+                (const c2_t<R> *)L.kron_lo, (const c2_t<R> *)L.kron_hi, L.kron_nlo);
+            return hipGetLastError();
+        }
+    }
+        k_stage<R, RB, false><<<(uint32_t)grid, threads, lds, s>>>(
+            (c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables, L.nchunks, L.xbits, (const c2_t<R> *)L.kron_lo,
+            (const c2_t<R> *)L.kron_hi, L.kron_nlo);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_stage_multi(const StageJobs &J, int C, hipStream_t s)
+hipError_t launch_stage_multi(const StageJobs &J, int C, bool quad, hipStream_t s)
 {
     constexpr int RB = sizeof(R) == 8 ? 4 : 5;
     if (C < RB + 6 || C > 16 || J.n == 0 || J.n > kStageJobsMax) return hipErrorInvalidValue;
@@ -514,20 +620,25 @@ hipError_t launch_stage_multi(const StageJobs &J, int C, hipStream_t s)
         if (J.first_block[j + 1] <= J.first_block[j] || J.job[j].state == nullptr || J.job[j].prog == nullptr)
             return hipErrorInvalidValue;
     if (J.first_block[0] != 0) return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_stage_multi<R, RB>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageLdsBytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
+    if constexpr (sizeof(R) == 8) {
+        if (quad) {
+            hipError_t e = stage_lds_attr<R, RB, true>();
+            if (e != hipSuccess) return e;
+            k_stage_multi<R, RB, true><<<J.first_block[J.n], threads, lds, s>>>(J);
+            return hipGetLastError();
+        }
+    } else if (quad) {
+        return hipErrorInvalidValue;
     }
-    k_stage_multi<R, RB><<<J.first_block[J.n], threads, lds, s>>>(J);
+    hipError_t e = stage_lds_attr<R, RB, false>();
+    if (e != hipSuccess) return e;
+    k_stage_multi<R, RB, false><<<J.first_block[J.n], threads, lds, s>>>(J);
     return hipGetLastError();
 }
 
 template hipError_t launch_stage<double>(const StageLaunch &, hipStream_t);
 template hipError_t launch_stage<float>(const StageLaunch &, hipStream_t);
-template hipError_t launch_stage_multi<double>(const StageJobs &, int, hipStream_t);
-template hipError_t launch_stage_multi<float>(const StageJobs &, int, hipStream_t);
+template hipError_t launch_stage_multi<double>(const StageJobs &, int, bool, hipStream_t);
+template hipError_t launch_stage_multi<float>(const StageJobs &, int, bool, hipStream_t);
 
 }  // namespace qs

@@ -50,12 +50,22 @@ double diag_cost(int w, int k, bool lane, bool c64)
     return base + (c64 ? r64[std::min(k, 5)] : r128[std::min(k, 5)]);
 }
 
+// A quadratic-phase operator (the product of many diagonals on one or two
+// qubits, applied as one phase form; complex128 stages only): microseconds
+// per 2^30 amplitudes.
+double quad_cost() { return 1200.0; }
+// The stage kernel variant with quadratic-phase operators runs the stage's
+// other work this much slower; the fixed part of a stage pass (loads,
+// stores, transposes) in the same units as the operator costs.
+constexpr double kQuadVariantPenalty = 0.06, kStageFixedUs = 2500.0;
+
 // Device seconds of one stage-kernel operator on `amps` amplitudes, in a
 // phase whose register bits sit at the physical qubits `reg` and whose lane
 // bits at `lane` (bit masks).
 double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64, uint64_t reg, uint64_t lane)
 {
     const double scale = amps / 1073741824.0 * 1e-6;
+    if (k.type == KOp::QUAD) return scale * quad_cost();
     if (k.type == KOp::DIAG) {
         int kr = 0;
         bool ln = false;
@@ -72,6 +82,10 @@ double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64, uint64_t r
 // Floating-point operations per amplitude: a dense k-qubit operator does 2^k
 // complex multiply-adds (8 flops each), a diagonal one complex multiply (6).
 double op_flops(bool diag, int dense_qubits) { return diag ? 6.0 : 8.0 * double(1 << dense_qubits); }
+
+// A quadratic phase: the running product that forms each amplitude's factor
+// and its application, one complex multiply each.
+constexpr double kQuadFlops = 12.0;
 
 }  // namespace
 
@@ -362,6 +376,12 @@ struct Builder {
             const size_t nm = ms.size();
             std::vector<char> used(nm, 0);
             size_t left = nm;
+            // members all on one or two qubits: one quadratic-phase operator
+            // when it costs less than the tables they pack into
+            bool quad = fuse && !c64 && (o.opt & SIM_OPT_QUAD) && o.window_qubits == 0 && nm > 1;
+            for (size_t i = 0; i < nm && quad; ++i) quad = ms[i].g->diag && ms[i].g->k() <= 2;
+            std::vector<KOp> packed;
+            double packed_us = 0;
             auto fits = [&](uint32_t S, uint64_t T) {
                 return popc(T) <= kZsel && popc(S) + popc(T) <= kZmax &&
                        popc(S) + popc(T & local_phys) <= kZloc;
@@ -403,8 +423,22 @@ struct Builder {
                 k.type = KOp::DIAG;
                 k.dq = qlist(S, tl);
                 for (size_t i : grp) k.members.push_back(*ms[i].g);
-                *flops_per_amp += op_flops(true, 0);
+                packed_us += diag_cost((int)k.dq.size(), popc(S), (T & lane_phys) != 0, c64);
+                packed.push_back(std::move(k));
+            }
+            if (quad && quad_cost() < packed_us) {
+                KOp k;
+                k.type = KOp::QUAD;
+                for (size_t i = 0; i < nm; ++i) k.members.push_back(*ms[i].g);
+                k.alt = std::move(packed);
+                k.alt_us = packed_us;
+                *flops_per_amp += kQuadFlops;
                 ph.ops.push_back(std::move(k));
+            } else {
+                for (KOp &k : packed) {
+                    *flops_per_amp += op_flops(true, 0);
+                    ph.ops.push_back(std::move(k));
+                }
             }
             ms.clear();
         };
@@ -727,6 +761,41 @@ struct Builder {
             st.phases.push_back(std::move(ph));
             prev = st.phases.back().reg;
             rem.swap(left);
+        }
+        // Quadratic-phase operators run on a kernel variant whose other work
+        // is slower (its register allocation; measured on MI355X): a stage
+        // keeps them only when they save more than that costs over the stage,
+        // else each goes back to the tables it replaced.
+        {
+            const double scale = std::ldexp(1.0, st.buffer_qubits) / 1073741824.0 * 1e-6;
+            double save = 0, quad_us = 0;
+            int nquad = 0;
+            for (const Phase &ph : st.phases)
+                for (const KOp &k : ph.ops)
+                    if (k.type == KOp::QUAD) {
+                        save += k.alt_us - quad_cost();
+                        quad_us += quad_cost();
+                        ++nquad;
+                    }
+            const double other_us = st.est_s / scale - quad_us + kStageFixedUs;
+            if (nquad && save < kQuadVariantPenalty * other_us) {
+                for (Phase &ph : st.phases) {
+                    std::vector<KOp> ops;
+                    for (KOp &k : ph.ops) {
+                        if (k.type != KOp::QUAD) {
+                            ops.push_back(std::move(k));
+                            continue;
+                        }
+                        fpa += op_flops(true, 0) * (double)k.alt.size() - kQuadFlops;
+                        for (KOp &t : k.alt) ops.push_back(std::move(t));
+                    }
+                    ph.ops.swap(ops);
+                }
+                st.est_s += scale * save;
+            } else {
+                for (Phase &ph : st.phases)
+                    for (KOp &k : ph.ops) k.alt.clear();
+            }
         }
         *flops += fpa;
         return rem;
@@ -1441,6 +1510,33 @@ std::vector<Operator> relabel_swaps(const std::vector<Operator> &gates, int n, s
 
 }  // namespace
 
+// Phase form of a product of diagonals on one or two qubits (entries of unit
+// modulus): with c = arg d(00), a diagonal d on qubits (q, p) has phase
+// c + (arg d(10) - c) x_q + (arg d(01) - c) x_p
+//   + (arg d(11) - arg d(10) - arg d(01) + c) x_q x_p
+// (entry index bit t <-> qubit t of the gate), and the phases of a product
+// add up.
+static void quad_coefficients(KOp &k, int n)
+{
+    k.qc = 0;
+    k.qa.assign(n, 0.0);
+    k.qb.assign((size_t)n * n, 0.0);
+    for (const Operator &g : k.members) {
+        const double c = std::arg(g.m[0]);
+        k.qc += c;
+        if (g.k() == 1) {
+            k.qa[g.q[0]] += std::arg(g.m[1]) - c;
+            continue;
+        }
+        const double d1 = std::arg(g.m[1]), d2 = std::arg(g.m[2]), d3 = std::arg(g.m[3]);
+        k.qa[g.q[0]] += d1 - c;
+        k.qa[g.q[1]] += d2 - c;
+        const int lo = std::min(g.q[0], g.q[1]), hi = std::max(g.q[0], g.q[1]);
+        k.qb[(size_t)lo * n + hi] += d3 - d1 - d2 + c;
+    }
+    k.members.clear();
+}
+
 void build_plan(Plan &plan, const std::vector<Operator> &gates)
 {
     auto t0 = std::chrono::steady_clock::now();
@@ -1471,7 +1567,9 @@ void build_plan(Plan &plan, const std::vector<Operator> &gates)
     for (PlanOp &op : plan.ops)  // tables of the accumulated diagonals of the kept lowering
         for (Phase &ph : op.phases)
             for (KOp &k : ph.ops)
-                if (!k.members.empty()) {
+                if (k.type == KOp::QUAD) {
+                    quad_coefficients(k, op.buffer_qubits);
+                } else if (!k.members.empty()) {
                     std::vector<const Operator *> ms;
                     for (const Operator &g : k.members) ms.push_back(&g);
                     k.table = diag_product(k.dq, ms).m;

@@ -22,8 +22,8 @@ KIND = {"U": 0, "MATRIX": 0, "DIAG": 1, "H": 2, "X": 3, "Y": 4, "Z": 5, "S": 6, 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(6)
 STATUS = {0: "OK", 1: "INVAL", 2: "NOMEM", 3: "DEVICE", 4: "STATE", 5: "UNSUPPORTED"}
 # optimisation flags
-OPT_DIAG, OPT_FUSE, OPT_STAGES, OPT_BOOST, OPT_REMAP = 1, 2, 4, 8, 16
-OPT_ALL = 31
+OPT_DIAG, OPT_FUSE, OPT_STAGES, OPT_BOOST, OPT_REMAP, OPT_QUAD = 1, 2, 4, 8, 16, 32
+OPT_ALL = 63
 # plan op kinds
 OP_NAMES = {0: "INIT", 1: "KRON", 2: "DENSE", 3: "DIAG", 4: "STAGE", 5: "PERM", 6: "WINDOW"}
 DTYPES = {"c128": 0, "c64": 1}
@@ -424,6 +424,14 @@ class Plan:
                         break
                     pl = np.empty(max(1, g.payload_len), dtype=np.complex128)
                     self._lib.sim_plan_stage_kernel_op(self._p, i, j, ctypes.byref(g), pl.ctypes.data)
+                    if g.diagonal == 2:
+                        # quadratic phase: (code, angle) terms, code -1 the
+                        # constant, 64 q + q linear in qubit q, 64 q + p a pair
+                        terms = [(int(round(v.real)), float(v.imag)) for v in pl[:g.payload_len]]
+                        kops.append({"diagonal": True, "quad": True, "qubits": [], "terms": terms,
+                                     "payload": None, "n_register": 0})
+                        j += 1
+                        continue
                     qs = [g.qubits[t] for t in range(g.nq)]
                     mat = pl[:g.payload_len].copy()
                     if not g.diagonal:

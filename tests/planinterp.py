@@ -27,6 +27,22 @@ def apply_diag(psi, n, qubits, table):
     return psi * table[y]
 
 
+def apply_quad(psi, n, terms):
+    """Phase exp(i phi(x)) with phi a quadratic form of the index bits, given
+    as (code, angle) terms: code -1 the constant, 64 q + q the linear term of
+    qubit q, 64 q + p (q < p) the term of the pair."""
+    x = np.arange(1 << n, dtype=np.int64)
+    phi = np.zeros(1 << n)
+    for code, ang in terms:
+        if code < 0:
+            phi += ang
+            continue
+        q, p = divmod(code, 64)
+        bits = (x >> q) & 1 if q == p else ((x >> q) & (x >> p)) & 1
+        phi += ang * bits
+    return psi * np.exp(1j * phi)
+
+
 def run_plan(ops, n, layout, use_kernel_ops=True):
     bufs = {}
     for op in ops:
@@ -52,7 +68,9 @@ def run_plan(ops, n, layout, use_kernel_ops=True):
         elif kind == "STAGE":
             seq = op["kernel_ops"] if (use_kernel_ops and op["n_phases"] > 0) else op["gates"]
             for g in seq:
-                if g["diagonal"]:
+                if g.get("quad"):
+                    bufs[b] = apply_quad(bufs[b], nb, g["terms"])
+                elif g["diagonal"]:
                     bufs[b] = apply_diag(bufs[b], nb, g["qubits"], g["payload"])
                 else:
                     bufs[b] = apply_dense(bufs[b], nb, g["qubits"], g["payload"])

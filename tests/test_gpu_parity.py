@@ -529,13 +529,40 @@ def test_benchmark_families_full_state(oracle_mod, family):
     for n in (14, 15):
         _, gates = W.config_circuit(f"{family}{n}")
         want = oracle_mod.run(n, gates)
-        for opt in (0, qsim.OPT_STAGES | qsim.OPT_REMAP, qsim.OPT_ALL):
+        for opt in (0, qsim.OPT_STAGES | qsim.OPT_REMAP, qsim.OPT_ALL & ~qsim.OPT_QUAD, qsim.OPT_ALL):
             say(f"{family}{n} c128 opt={opt}")
             got, _ = gpu_state(n, gates, opt=opt, C=12)
             check128(got, want, f"{family}{n} opt={opt}")
         say(f"{family}{n} c64")
         got, _ = gpu_state(n, gates, dtype="c64", opt=qsim.OPT_ALL)
         check64(got, want, oracle_mod, f"{family}{n} c64")
+
+
+def test_quadratic_phase_operator(oracle_mod):
+    """Complex128 stages whose register phases collect many one- and two-qubit
+    diagonals apply them as one quadratic-phase operator (chunk rows,
+    per-thread rows, Gray-code walk over the register tile): every chunk size
+    against the oracle, with the plan checked to use the operator; complex64
+    (diagonal tables) on the same circuits."""
+    # (n, circuit, chunk sizes at which the complex128 plan must use the operator)
+    cases = [(16, W.rzz_full(16, 4), (11, 12, 13)),
+             (17, W.qft(17, 6), (10, 11, 12, 13)),
+             (17, W.qaoa_full(17, 2, 3), ()),
+             (15, W.diag_heavy(15, 300, 9, 0.85), ())]
+    for n, gates, expect in cases:
+        want = oracle_mod.run(n, gates)
+        for dtype, Cs in (("c128", (10, 11, 12, 13)), ("c64", (11, 12, 13, 14))):
+            for C in Cs:
+                ops = qsim.Plan(n, gates, dtype=dtype, C=C).ops()
+                nquad = sum(1 for o in ops if o["kind"] == "STAGE" for k in o["kernel_ops"] if k.get("quad"))
+                say(f"quad n={n} {dtype} C={C}: {nquad} operators")
+                got, _ = gpu_state(n, gates, dtype=dtype, opt=qsim.OPT_ALL, C=C)
+                if dtype == "c128":
+                    check128(got, want, f"quad n={n} C={C}")
+                else:
+                    check64(got, want, oracle_mod, f"quad n={n} c64 C={C}")
+                if dtype == "c128" and C in expect:
+                    assert nquad >= 1, (n, C)
 
 
 @pytest.mark.parametrize("family", ["rzz", "qft", "qaoa"])

@@ -12,7 +12,7 @@ from paper_2604_12256_amd.workloads import Gate
 
 from .planinterp import access_count, run_plan
 
-ALL_OPTS = list(range(16)) + [31, 16 | 4, 16 | 6, 16 | 12, 16 | 14]
+ALL_OPTS = list(range(16)) + [31, 63, 16 | 4, 16 | 6, 16 | 12, 16 | 14, 32 | 6, 32 | 7, 32 | 14]
 
 
 def plan_state(n, gates, **kw):
@@ -414,7 +414,7 @@ def test_phase_diagonals_merge_into_wide_tables(oracle_mod):
     for gates in (W.qaoa_full(n, 2, 3), W.rzz_full(n, 4) + W.layered(n, 2, 5), W.qft(n, 6)):
         want = oracle_mod.run(n, gates)
         for dtype, C in (("c128", 10), ("c64", 11), ("c128", 12)):
-            p = qsim.Plan(n, gates, dtype=dtype, C=C)
+            p = qsim.Plan(n, gates, dtype=dtype, C=C, opt=qsim.OPT_ALL & ~qsim.OPT_QUAD)
             ops = p.ops()
             widths = [len(k["qubits"]) for o in ops if o["kind"] == "STAGE"
                       for k in o["kernel_ops"] if k["diagonal"]]

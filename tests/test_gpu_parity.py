@@ -448,6 +448,35 @@ def test_batched_mid_size_circuits_staged(oracle_mod):
         sim.close()
 
 
+def test_batched_stages_with_quadratic_phases(oracle_mod):
+    """A staged batch whose stage programs hold quadratic-phase operators
+    (RZZ and QFT circuits) next to ones that do not: the launches that carry
+    them run the kernel variant with the operator; every state equals its
+    solo run bitwise and the oracle."""
+    import torch
+    cases = []
+    for i, n in enumerate((15, 16, 17, 16, 15)):
+        gates = (W.rzz_full(n, 20 + i), W.qft(n, 30 + i), W.layered(n, 4, 40 + i),
+                 W.rzz_full(n, 50 + i), W.qft(n, 60 + i))[i]
+        sim = qsim.Simulator(n, opt=qsim.OPT_ALL)
+        sim.load(gates)
+        cases.append((n, gates, sim))
+    nquad = 0
+    for n, gates, _ in cases:
+        ops = qsim.Plan(n, gates).ops()
+        nquad += sum(1 for o in ops if o["kind"] == "STAGE" for k in o["kernel_ops"] if k.get("quad"))
+    assert nquad >= 3
+    say(f"staged batch with {nquad} quadratic-phase operators")
+    qsim.run_batch([c[2] for c in cases])
+    torch.cuda.synchronize()
+    got = [c[2].amplitudes() for c in cases]
+    for (n, gates, sim), g in zip(cases, got):
+        check128(g, oracle_mod.run(n, gates), f"quad batch n={n}")
+        sim.run()
+        assert np.array_equal(sim.amplitudes(), g), f"quad batch n={n} differs from its solo run"
+        sim.close()
+
+
 def qsim_small_max(dtype):
     return 13 if dtype == "c128" else 14
 

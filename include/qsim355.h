@@ -85,8 +85,8 @@ enum {
     SIM_OPT_QUAD = 1u << 5,    /* with FUSE: the one- and two-qubit diagonals a register phase
                                   collects become one quadratic-phase operator (phase
                                   c + sum a_q x_q + sum b_qp x_q x_p) when that costs less than
-                                  their diagonal tables; complex128 only, not used with
-                                  host-memory offload */
+                                  their diagonal tables; not used with host-memory
+                                  offload */
     SIM_OPT_ALL = 0x3Fu
 };
 

@@ -876,7 +876,11 @@ template <typename R>
 sim_status execute_staged_batch(sim_ctx *const *cs, uint32_t n, hipStream_t st)
 {
     std::vector<size_t> cur(n, 0);
-    auto batched = [](const Prepared &p) { return p.kind == SIM_OP_STAGE && !p.small && p.buffer == 0; };
+    // complex64 stages with quadratic-phase operators run one state per
+    // launch (the batched kernel has no complex64 variant with them)
+    auto batched = [](const Prepared &p) {
+        return p.kind == SIM_OP_STAGE && !p.small && p.buffer == 0 && !(sizeof(R) == 4 && p.quad);
+    };
     for (;;) {
         bool left = false;
         for (uint32_t k = 0; k < n; ++k) {

@@ -314,7 +314,8 @@ __device__ __forceinline__ void transpose(c2_t<R> *amp, uint32_t lds_base, uint3
 
 // Quadratic-phase operator (op type 3): amplitude x is multiplied by
 // e^{i phi(x)}, phi(x) = c + sum a_q x_q + sum b_qp x_q x_p over the buffer's
-// qubits, for complex128 stages.  Its block of complex FP64
+// qubits, formed in FP64 (also for complex64 states, whose amplitudes take
+// one FP32 rounding per operator).  Its block of complex FP64
 // unit factors (in the program words) holds, for the chunk's share, rows
 // selected by the low and the high half of the chunk index: lane l < C forms
 // B_l = e^{i beta_l} (the coefficient the chunk bits give local bit l) as the
@@ -562,9 +563,12 @@ template <typename R, int RB, bool QD> hipError_t stage_lds_attr()
     if (done) return hipSuccess;
     hipError_t e = hipFuncSetAttribute((const void *)k_stage<R, RB, QD>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kStageLdsBytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_stage_multi<R, RB, QD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kStageLdsBytes);
+    // the batched kernel with quadratic-phase operators exists for complex128
+    // only (in complex64 it would need scratch memory)
+    if constexpr (!QD || sizeof(R) == 8)
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_stage_multi<R, RB, QD>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageLdsBytes);
     done = e == hipSuccess;
     return e;
 }
@@ -580,12 +584,7 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     const uint32_t threads = 1u << (C - RB);
     const uint32_t lds = (uint32_t)sizeof(c2_t<R>) << C;
     if (threads > (uint32_t)kStageMaxThreads || lds > kStageLdsBytes) return hipErrorInvalidValue;
-    // quadratic-phase operators exist for complex128 stages only
-    if constexpr (sizeof(R) != 8)
-        if (L.quad) return hipErrorInvalidValue;
-    hipError_t e = hipSuccess;
-    if constexpr (sizeof(R) == 8) e = L.quad ? stage_lds_attr<R, RB, true>() : stage_lds_attr<R, RB, false>();
-    else e = stage_lds_attr<R, RB, false>();
+    hipError_t e = L.quad ? stage_lds_attr<R, RB, true>() : stage_lds_attr<R, RB, false>();
     if (e != hipSuccess) return e;
     // at most 2^15 workgroups: on large states each walks several chunks, so
     // its set-up (thread bases, mapping tables) is paid once per several
@@ -594,13 +593,11 @@ hipError_t launch_stage(const StageLaunch &L, hipStream_t s)
     uint64_t grid = L.nchunks;
     if (grid > (1ull << 15)) grid = 1ull << 15;
     if (L.kron_lo && (L.kron_nlo < 1 || L.kron_nlo >= L.n || !L.kron_hi)) return hipErrorInvalidValue;
-    if constexpr (sizeof(R) == 8) {
-        if (L.quad) {
-            k_stage<R, RB, true><<<(uint32_t)grid, threads, lds, s>>>(
-                (c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables, L.nchunks, L.xbits,
-                (const c2_t<R> *)L.kron_lo, (const c2_t<R> *)L.kron_hi, L.kron_nlo);
-            return hipGetLastError();
-        }
+    if (L.quad) {
+        k_stage<R, RB, true><<<(uint32_t)grid, threads, lds, s>>>(
+            (c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables, L.nchunks, L.xbits, (const c2_t<R> *)L.kron_lo,
+            (const c2_t<R> *)L.kron_hi, L.kron_nlo);
+        return hipGetLastError();
     }
         k_stage<R, RB, false><<<(uint32_t)grid, threads, lds, s>>>(
             (c2_t<R> *)L.state, L.prog, (const c2_t<R> *)L.tables, L.nchunks, L.xbits, (const c2_t<R> *)L.kron_lo,

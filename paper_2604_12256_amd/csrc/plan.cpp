@@ -51,9 +51,10 @@ double diag_cost(int w, int k, bool lane, bool c64)
 }
 
 // A quadratic-phase operator (the product of many diagonals on one or two
-// qubits, applied as one phase form; complex128 stages only): microseconds
-// per 2^30 amplitudes.
-double quad_cost() { return 1200.0; }
+// qubits, applied as one phase form, in FP64): microseconds per 2^30
+// amplitudes.
+constexpr double kQuadCostC64 = 600.0;
+double quad_cost(bool c64) { return c64 ? kQuadCostC64 : 1200.0; }
 // The stage kernel variant with quadratic-phase operators runs the stage's
 // other work this much slower; the fixed part of a stage pass (loads,
 // stores, transposes) in the same units as the operator costs.
@@ -65,7 +66,7 @@ constexpr double kQuadVariantPenalty = 0.06, kStageFixedUs = 2500.0;
 double kop_seconds(const KOp &k, int reg_bits, double amps, bool c64, uint64_t reg, uint64_t lane)
 {
     const double scale = amps / 1073741824.0 * 1e-6;
-    if (k.type == KOp::QUAD) return scale * quad_cost();
+    if (k.type == KOp::QUAD) return scale * quad_cost(c64);
     if (k.type == KOp::DIAG) {
         int kr = 0;
         bool ln = false;
@@ -378,7 +379,7 @@ struct Builder {
             size_t left = nm;
             // members all on one or two qubits: one quadratic-phase operator
             // when it costs less than the tables they pack into
-            bool quad = fuse && !c64 && (o.opt & SIM_OPT_QUAD) && o.window_qubits == 0 && nm > 1;
+            bool quad = fuse && (o.opt & SIM_OPT_QUAD) && o.window_qubits == 0 && nm > 1;
             for (size_t i = 0; i < nm && quad; ++i) quad = ms[i].g->diag && ms[i].g->k() <= 2;
             std::vector<KOp> packed;
             double packed_us = 0;
@@ -426,7 +427,7 @@ struct Builder {
                 packed_us += diag_cost((int)k.dq.size(), popc(S), (T & lane_phys) != 0, c64);
                 packed.push_back(std::move(k));
             }
-            if (quad && quad_cost() < packed_us) {
+            if (quad && quad_cost(c64) < packed_us) {
                 KOp k;
                 k.type = KOp::QUAD;
                 for (size_t i = 0; i < nm; ++i) k.members.push_back(*ms[i].g);
@@ -773,8 +774,8 @@ struct Builder {
             for (const Phase &ph : st.phases)
                 for (const KOp &k : ph.ops)
                     if (k.type == KOp::QUAD) {
-                        save += k.alt_us - quad_cost();
-                        quad_us += quad_cost();
+                        save += k.alt_us - quad_cost(plan.dtype == SIM_C64);
+                        quad_us += quad_cost(plan.dtype == SIM_C64);
                         ++nquad;
                     }
             const double other_us = st.est_s / scale - quad_us + kStageFixedUs;

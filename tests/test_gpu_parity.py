@@ -594,6 +594,22 @@ def test_quadratic_phase_operator(oracle_mod):
                     assert nquad >= 1, (n, C)
 
 
+def test_quadratic_phase_operator_complex64(oracle_mod):
+    """The quadratic-phase operator in complex64 stages (FP64 factors, one
+    FP32 rounding per amplitude): 22-qubit RZZ and QAOA circuits whose
+    complex64 plans use it at every chunk size, against the oracle."""
+    n = 22
+    for name, gates in (("rzz22", W.rzz_full(n, 4)), ("qaoa22", W.qaoa_full(n, 2, 3))):
+        want = oracle_mod.run(n, gates)
+        for C in (11, 13, 14):
+            ops = qsim.Plan(n, gates, dtype="c64", C=C).ops()
+            nquad = sum(1 for o in ops if o["kind"] == "STAGE" for k in o["kernel_ops"] if k.get("quad"))
+            say(f"quad {name} c64 C={C}: {nquad} operators")
+            assert nquad >= 1, (name, C)
+            got, _ = gpu_state(n, gates, dtype="c64", opt=qsim.OPT_ALL, C=C)
+            check64(got, want, oracle_mod, f"quad {name} c64 C={C}")
+
+
 @pytest.mark.parametrize("family", ["rzz", "qft", "qaoa"])
 def test_benchmark_families_30q_closed_form(family):
     """The same families at 30 qubits against their closed forms (diagonal

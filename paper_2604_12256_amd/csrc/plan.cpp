@@ -794,8 +794,22 @@ struct Builder {
                 }
                 st.est_s += scale * save;
             } else {
-                for (Phase &ph : st.phases)
-                    for (KOp &k : ph.ops) k.alt.clear();
+                // a phase of quadratic-phase operators alone on the load
+                // mapping's register bits takes the load mapping's thread
+                // order too (the operator reads any order), so the chunk
+                // needs no transpose into or out of it
+                const uint64_t neutral = ((1ull << r) - 1) << (C - r);
+                for (Phase &ph : st.phases) {
+                    bool only = !ph.ops.empty();
+                    uint64_t R = 0;
+                    for (KOp &k : ph.ops) {
+                        k.alt.clear();
+                        only &= k.type == KOp::QUAD;
+                    }
+                    for (int i : ph.reg) R |= 1ull << i;
+                    if (only && R == neutral)
+                        for (int i = 0; i < C - r; ++i) ph.tmap[i] = i;
+                }
             }
         }
         *flops += fpa;

@@ -328,7 +328,11 @@ typedef struct {
 /* A gate as executed inside a stage or a sub-state run, after fusion:
  * a dense or diagonal operator on `nq` physical qubits of its buffer. */
 typedef struct {
-    uint32_t diagonal;      /* 1: payload is a 2^nq diagonal; 0: 2^nq x 2^nq matrix */
+    uint32_t diagonal;      /* 1: payload is a 2^nq diagonal; 0: 2^nq x 2^nq matrix;
+                               2 (stage-kernel operators only): a quadratic phase
+                               e^{i phi(x)}, nq = 0, payload = (code, angle) pairs as
+                               (re, im): code -1 the constant, 64 q + q the linear term
+                               of qubit q, 64 q + p (q < p) the pair term */
     uint32_t nq;
     uint32_t qubits[16];
     uint64_t payload_len;

@@ -439,10 +439,26 @@ __device__ __forceinline__ void stage_chunks(c2_t<R> *__restrict__ state, const 
         V *const pt = state + (cbase | tphys);
         if (klo) {
             const uint64_t lomask = (1ull << knlo) - 1;
+            const uint64_t base = cbase | tphys;
+            uint64_t rbits = 0;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const uint64_t x = cbase | tphys | reg_phys_offset<RB>(j, regphys);
-                amp[j] = cmul(klo[x & lomask], khi[x >> knlo]);
+            for (int b = 0; b < RB; ++b) rbits |= regphys[b];
+            if (!(rbits & lomask)) {
+                // register bits all in the high factor: one low factor per thread
+                const V lo = klo[base & lomask];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) amp[j] = cmul(lo, khi[(base | reg_phys_offset<RB>(j, regphys)) >> knlo]);
+            } else if (!(rbits >> knlo)) {
+                // register bits all in the low factor: one high factor per thread
+                const V hi = khi[base >> knlo];
+#pragma unroll
+                for (int j = 0; j < NR; ++j) amp[j] = cmul(klo[(base | reg_phys_offset<RB>(j, regphys)) & lomask], hi);
+            } else {
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const uint64_t x = base | reg_phys_offset<RB>(j, regphys);
+                    amp[j] = cmul(klo[x & lomask], khi[x >> knlo]);
+                }
             }
         } else {
 #pragma unroll

@@ -527,3 +527,26 @@ def test_phase_cap_splits_the_stage(oracle_mod, n):
     want = oracle_mod.run(n, gates)
     assert np.max(np.abs(got_k - want)) < 1e-12
     assert np.max(np.abs(got_g - want)) < 1e-12
+
+
+def test_quadratic_phase_operator_plans(oracle_mod):
+    """Plans whose register phases turn one- and two-qubit diagonals into a
+    quadratic-phase operator: the exported (term, angle) form, applied as
+    e^{i phi(x)} by the interpreter, reproduces the oracle's state; without
+    the option the same circuits keep diagonal tables."""
+    for n, gates in ((16, W.rzz_full(16, 4)), (17, W.qft(17, 6))):
+        want = oracle_mod.run(n, gates)
+        for dtype in ("c128", "c64"):
+            C = 12 if dtype == "c128" else 13
+            p = qsim.Plan(n, gates, dtype=dtype, C=C)
+            ops = p.ops()
+            quads = [k for o in ops if o["kind"] == "STAGE" for k in o["kernel_ops"] if k.get("quad")]
+            if dtype == "c128":
+                assert quads, n
+            for k in quads:
+                codes = [c for c, _ in k["terms"]]
+                assert codes[0] == -1 and len(set(codes)) == len(codes)
+                assert all(c == -1 or (c // 64 <= c % 64 < n) for c in codes)
+            assert np.max(np.abs(run_plan(ops, n, p.layout()) - want)) < 1e-12, (n, dtype)
+            q = qsim.Plan(n, gates, dtype=dtype, C=C, opt=qsim.OPT_ALL & ~qsim.OPT_QUAD)
+            assert not any(k.get("quad") for o in q.ops() if o["kind"] == "STAGE" for k in o["kernel_ops"])
